@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs for the real-time Kohn-Sham step.
+
+This package only builds input arrays (orbitals, local potential, projectors,
+coupling constants, occupations, the laser vector potential).  It performs none
+of the propagation arithmetic, so both the FP64 CPU oracle and the HIP library
+can consume the same inputs without sharing any of the method's code.
+"""
+from .workloads import (  # noqa: F401
+    Domain,
+    Workload,
+    make_domain,
+    pulse_midpoints,
+    config,
+    batched_domain_shapes,
+    batched_domain,
+)
