@@ -1,0 +1,163 @@
+"""Benchmark of the real-time Kohn-Sham step on one MI355X.
+
+Default workload: one 64^3 periodic domain (h = 0.4 bohr), 128 complex64
+orbitals, 64 atoms x 8 projectors (512 columns), 6th-order finite differences,
+laser vector potential A_z(t) = 0.05 sin(0.1 t) sin^2(pi t / 4 a.u.) at the step
+midpoints, dt = 0.02; plain FP32 path, density, current and energy every step.
+
+A "step" is one Taylor-4 step: four applications of H (stencil + both
+projector products) and the per-step density/current/energy.  The metric is
+orbital-gridpoint H.psi updates per second = N_g * N_o * 4 * steps / time.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+
+Prints one JSON line.  Kernel times come from HIP events that the library
+records around every launch on the call's stream (DCMESH_FLAG_PROFILE) during
+the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "split_bf16": 2500.0, "split_fp16": 2500.0}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(dom, a_mid, dt, n_orb_sample=16):
+    """The FP64 oracle on the host: one Taylor-4 step of the same domain
+    restricted to its first ``n_orb_sample`` orbitals (orbitals propagate
+    independently, so the per-orbital cost is that of the full step)."""
+    from oracle import propagate as P
+    from synth import Domain
+    sub = Domain(dom.shape, dom.h, dom.fd_order, np.ascontiguousarray(dom.psi[:, :n_orb_sample]),
+                 dom.v_loc, dom.proj, dom.d, dom.occ[:n_orb_sample])
+    t0 = time.perf_counter()
+    P.taylor4_step(sub, a_mid[0], dt, sub.psi)
+    t = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    return {"value": dom.n_grid * n_orb_sample * 4 / t, "unit": "orbital-gridpoint updates/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"one Taylor-4 step (4 H applications) of the 64^3/512-projector domain on "
+                      f"{n_orb_sample} of its 128 orbitals, FP64 numpy; {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "split_bf16", "split_fp16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the step has no cross-GPU part in this build "
+              "(domains are independent; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2509_00966_amd as api
+    from synth import config, pulse_midpoints
+
+    log("bench: generating the 64^3 / 128-orbital / 512-projector domain")
+    w = config(2)
+    dom = w.domains[0]
+    K, W = args.steps, args.warmup
+    a_mid = pulse_midpoints(max(200, K + W), w.dt, 200)
+    prec = args.precision
+    cd, rd = api.complex_dtype(prec), api.real_dtype(prec)
+    dev = "cuda:0"
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x)).to(dev, dt)
+    g = api.Domain(dom.shape, dom.fd_order, dom.h, t(dom.psi, cd), t(dom.v_loc, rd), t(dom.proj, cd),
+                   t(dom.d, rd), t(dom.occ, rd))
+    ws = api.Workspace.for_domains([g], prec)
+    ng, no, npj = dom.n_grid, dom.n_orb, dom.n_proj
+    a_dev = t(a_mid, torch.float64)
+    obs = dict(rho=torch.zeros(K, ng, dtype=rd, device=dev), j=torch.zeros(K, ng, 3, dtype=rd, device=dev),
+               energy=torch.zeros(K, dtype=torch.float64, device=dev))
+    obs_w = dict(rho=torch.zeros(max(W, 1), ng, dtype=rd, device=dev),
+                 j=torch.zeros(max(W, 1), ng, 3, dtype=rd, device=dev),
+                 energy=torch.zeros(max(W, 1), dtype=torch.float64, device=dev))
+    log(f"bench: warmup {W} steps")
+    if W:
+        api.step([g], a_dev[:W].contiguous(), w.dt, W, prec, ws, obs=[obs_w])
+    torch.cuda.synchronize()
+    api.profile_collect()
+    log(f"bench: timing {K} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    api.step([g], a_dev[W:W + K].contiguous(), w.dt, K, prec, ws, obs=[obs], profile=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = api.profile_collect()
+    log("bench: kernel times " + json.dumps({k: [round(v[0], 3), v[1]] for k, v in prof.items() if v[1]}))
+
+    ms_step = elapsed * 1e3 / K
+    updates = ng * no * 4 * K / elapsed
+    flops_gemm = 8.0 * ng * no * npj              # per projection or correction launch
+    bytes_stencil = ng * no * 24.0 + ng * 4.0     # read u, read psi, write out, read V
+    kernels = {}
+    for fam, (ms, cnt) in prof.items():
+        if not cnt:
+            continue
+        avg = ms / cnt
+        entry = {"launches": cnt, "avg_ms": avg, "total_ms": ms}
+        if fam in ("project", "correct"):
+            entry.update(bound="mfma", achieved=flops_gemm / (avg * 1e-3) / 1e12, unit="TFLOP/s",
+                         peak=PEAK_TFLOPS[prec])
+        elif fam == "stencil":
+            entry.update(bound="hbm", achieved=bytes_stencil / (avg * 1e-3) / 1e9, unit="GB/s", peak=PEAK_HBM_GBS)
+        if "peak" in entry:
+            entry["frac"] = entry["achieved"] / entry["peak"]
+        kernels[fam] = entry
+    dom_fam = max((f for f in kernels if "peak" in kernels[f]), key=lambda f: kernels[f]["total_ms"])
+    dk = kernels[dom_fam]
+    roofline = {"kernel": dom_fam, "bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
+                "unit": dk["unit"], "frac": dk["frac"], "traffic": None}
+
+    finite = bool(torch.isfinite(g.psi).all().item())
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on a bounded sample")
+        cpu = cpu_baseline(dom, a_mid, w.dt)
+    out = {
+        "metric": "orbital-gridpoint H.psi updates/s",
+        "value": updates,
+        "unit": "orbital-gridpoint updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "fp32", "fp64": "fp64", "split_bf16": "bf16x2+fp32", "split_fp16": "fp16x2+fp32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "single domain 64^3, h=0.4, 128 complex64 orbitals, 64 atoms x 8 projectors, "
+                               "FD6, laser A_z(t), dt=0.02, Taylor-4, rho+j+E every step",
+                   "precision": prec, "n_grid": ng, "n_orb": no, "n_proj": npj},
+        "roofline": roofline,
+        "kernels": kernels,
+        "s_per_orbital_step": elapsed / K / no,
+        "psi_finite": finite,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

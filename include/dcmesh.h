@@ -1,0 +1,197 @@
+/*
+ * dcmesh.h -- C ABI of the MI355X real-time Kohn-Sham step library.
+ *
+ * The library advances complex Kohn-Sham orbitals on periodic real-space grids
+ * ("domains" of the divide-and-conquer scheme, Sec. V.A.1) by the step
+ *     psi <- T4(-i dt H(A_k)) psi,   T4(z) = sum_{m=0}^{4} z^m / m!,
+ * the fourth-order Taylor form of exp(-i dt H) (Eq. 2 with the full H), with
+ *     H(A) = -1/2 Lap_h - i A.grad_h + 1/2 |A|^2 + v_loc + B diag(D) h^3 B^H
+ * (Eq. 3 in atomic units: hbar = m = 1, e/c folded into A; the nonlocal part as
+ * the two dense products of Sec. V.B.5).  Lap_h and grad_h are periodic central
+ * finite differences of order 2, 4 or 6.  A_k is the vector potential at the
+ * step midpoint t_k + dt/2 (the midpoint rule of Eq. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid point g = (z*ny + y)*nx + x sits at r = h*(x, y, z).  Inner product
+ * <a|b> = h^3 sum_g conj(a_g) b_g.
+ * Layouts (row-major, the orbital index fastest: the structure-of-arrays
+ * layout of Sec. V.B.2):
+ *     psi   [N_g][n_orb]  complex (interleaved re, im)
+ *     proj  [N_g][n_proj] complex  (columns beta_p)
+ *     v_loc [N_g], d [n_proj], occ [n_orb]  real
+ * Element types follow the precision mode:
+ *     DCMESH_FP64                         complex128 / float64
+ *     DCMESH_FP32, DCMESH_SPLIT_BF16/FP16  complex64  / float32
+ * Energies, gradients, overlaps and A samples are always float64.
+ *
+ * Ownership: every pointer inside a call's arguments is caller-owned device
+ * memory (unless stated as host) and must stay valid until the work queued on
+ * the stream has finished.  The library allocates no device memory; scratch
+ * space is the caller's workspace, sized by dcmesh_workspace_bytes, whose
+ * contents are private to the library between calls.  The library keeps no
+ * device pointer after a call returns, except inside a graph handle.
+ *
+ * Streams: all work is queued on the given stream (a hipStream_t passed as
+ * void*, NULL = the default stream) and calls return without waiting for it.
+ * No entry point synchronises, allocates or reads device memory on the host
+ * unless DCMESH_FLAG_CHECK_FINITE is set, so the calls can be captured into a
+ * HIP graph.
+ *
+ * Errors: each entry point returns a DCMESH_* status; 0 means success.  All
+ * arguments are validated on the host before any HIP call, so an invalid
+ * argument leaves the stream untouched.  dcmesh_last_error() gives a message
+ * for the calling thread's last failure.
+ */
+#ifndef DCMESH_H
+#define DCMESH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum dcmesh_status {
+  DCMESH_OK = 0,
+  DCMESH_ERR_INVALID_ARGUMENT = 1,  /* a null pointer, a bad size or order */
+  DCMESH_ERR_UNSUPPORTED = 2,       /* a valid request this build cannot run */
+  DCMESH_ERR_WORKSPACE = 3,         /* workspace missing, too small or misaligned */
+  DCMESH_ERR_HIP = 4,               /* a HIP runtime call failed */
+  DCMESH_ERR_NONFINITE = 5          /* CHECK_FINITE found a NaN/Inf in psi */
+};
+
+enum dcmesh_precision {
+  DCMESH_FP64 = 0,        /* complex128 everywhere, FP64 matrix cores */
+  DCMESH_FP32 = 1,        /* complex64; projector products on FP32 matrix cores */
+  DCMESH_SPLIT_BF16 = 2,  /* complex64; projector products as BF16 hi+lo, FP32 accumulation */
+  DCMESH_SPLIT_FP16 = 3   /* complex64; projector products as FP16 hi+lo (power-of-two scaled) */
+};
+
+/* Flags (bitwise or). */
+#define DCMESH_FLAG_CHECK_FINITE 0x1u  /* synchronise after the call and test psi for NaN/Inf */
+#define DCMESH_FLAG_PROFILE 0x2u       /* bracket every kernel launch with HIP events on the
+                                          call's stream; read with dcmesh_profile_collect */
+
+/* Kernel families reported by dcmesh_profile_collect. */
+enum dcmesh_family {
+  DCMESH_FAM_STENCIL = 0,   /* local H sweep fused with the Taylor-stage update */
+  DCMESH_FAM_PROJECT = 1,   /* P = h^3 B^H u, split-K partials */
+  DCMESH_FAM_REDUCE = 2,    /* split-K sum, coef D P and its real form */
+  DCMESH_FAM_CORRECT = 3,   /* out += B (coef D P) */
+  DCMESH_FAM_DENSITY = 4,   /* rho and j */
+  DCMESH_FAM_ENERGY = 5,    /* energy finalisation */
+  DCMESH_FAM_ADJOINT = 6,   /* gradient inner products and lambda accumulation */
+  DCMESH_FAM_OVERLAP = 7,   /* S = h^3 Psi^H Psi */
+  DCMESH_N_FAMILIES = 8
+};
+
+/* One periodic domain.  nx, ny, nz >= fd_order + 1; fd_order in {2, 4, 6};
+ * n_orb >= 1; n_proj >= 0 (0: no nonlocal term, proj and d may be NULL). */
+typedef struct dcmesh_domain {
+  int32_t nx, ny, nz;
+  int32_t fd_order;
+  int32_t n_orb;
+  int32_t n_proj;
+  double h;               /* mesh spacing (bohr), > 0 */
+  void* psi;              /* [N_g][n_orb] complex, in/out */
+  const void* v_loc;      /* [N_g] real (Ha) */
+  const void* proj;       /* [N_g][n_proj] complex */
+  const void* d;          /* [n_proj] real (Ha) */
+  const void* occ;        /* [n_orb] real occupations f_n */
+} dcmesh_domain;
+
+/* Per-step observables of one domain for dcmesh_step.  Entry k refers to the
+ * state entering step k, evaluated with that step's field A_k.  Any pointer may
+ * be NULL (not computed).
+ *   rho    [n_steps][N_g]     real   rho = sum_n f_n |psi_n|^2
+ *   j      [n_steps][N_g][3]  real   j = sum_n f_n [Im(conj psi_n grad_h psi_n) + A |psi_n|^2]
+ *   energy [n_steps]          float64  E = h^3 sum_n f_n <psi_n|H(A_k)|psi_n> */
+typedef struct dcmesh_obs {
+  void* rho;
+  void* j;
+  double* energy;
+} dcmesh_obs;
+
+/* Outputs of dcmesh_density for one domain (any may be NULL).
+ *   rho [N_g], j [N_g][3]  real, as in dcmesh_obs
+ *   energy                 one float64, E = h^3 sum_n f_n <psi_n|H(A)|psi_n>
+ *   hpsi_occ [N_g][n_orb]  complex, f_n H(A) psi_n (the adjoint seed of E)
+ *   overlap [n_orb][n_orb] complex128, S = h^3 Psi^H Psi accumulated in FP64 */
+typedef struct dcmesh_density_out {
+  void* rho;
+  void* j;
+  double* energy;
+  void* hpsi_occ;
+  double* overlap;
+} dcmesh_density_out;
+
+/* Workspace needed by dcmesh_step, dcmesh_density and dcmesh_adjoint_step for
+ * these domains and precision (one size serves all three).  Host-only; writes
+ * *bytes.  Workspace pointers must be 256-byte aligned. */
+int dcmesh_workspace_bytes(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                           uint32_t flags, size_t* bytes);
+
+/* Advance every domain by n_steps Taylor-4 steps (Eq. 2 structure, full H).
+ *   doms      host array [n_dom]
+ *   a_dev     device float64 A samples, [n_a][a_stride][3] with n_a = n_dom if
+ *             a_per_domain else 1; step k of this call uses a_dev[.][k][:]
+ *   dt        time step (a.u.); n_steps >= 0
+ *   obs       NULL or host array [n_dom] of per-step observable outputs
+ *   work      device workspace of work_bytes >= dcmesh_workspace_bytes(...)
+ *   stream    hipStream_t */
+int dcmesh_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                const double* a_dev, int32_t a_per_domain, int64_t a_stride,
+                double dt, int32_t n_steps, const dcmesh_obs* obs,
+                void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* Observables of the current orbitals for the field a_dev ([n_a][3], float64,
+ * device).  out: host array [n_dom]. */
+int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                   const double* a_dev, int32_t a_per_domain,
+                   const dcmesh_density_out* out,
+                   void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* One step of the adjoint recursion for the gradient of a loss L(psi_N):
+ *     lambda_k = U_k^H lambda_{k+1} = T4(+i dt H(A_k)) lambda_{k+1}
+ *     grad[d] += 2 Re <lambda_{k+1}, (dU_k/dA_d) psi_k>,  dH/dA_d = -i D1_d + A_d
+ * doms[i].psi holds psi_k (read only).  lambda: host array [n_dom] of device
+ * pointers, [N_g][n_orb] complex, overwritten in place.  a_dev: A_k,
+ * [n_a][3] float64.  grad_dev: device float64 [n_a][3], accumulated (+=). */
+int dcmesh_adjoint_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                        void* const* lambda, const double* a_dev, int32_t a_per_domain,
+                        double dt, double* grad_dev,
+                        void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* Record the work of one dcmesh_step call (same arguments) into a HIP graph
+ * owned by the returned handle; replay it with dcmesh_graph_launch.  The
+ * handle keeps the pointers it was built with. */
+int dcmesh_graph_create(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                        const double* a_dev, int32_t a_per_domain, int64_t a_stride,
+                        double dt, int32_t n_steps, const dcmesh_obs* obs,
+                        void* work, size_t work_bytes, uint32_t flags, void* stream,
+                        void** graph_out);
+int dcmesh_graph_launch(void* graph, void* stream);
+int dcmesh_graph_destroy(void* graph);
+
+/* Tile choices: dcmesh_set_tuning selects a kernel variant for a kernel family
+ * (DCMESH_KERNEL_*) and value (see dcmesh_tuning_options); -1 restores the
+ * built-in heuristic.  Process-wide; takes effect for calls made afterwards. */
+enum dcmesh_kernel { DCMESH_KERNEL_STENCIL = 0, DCMESH_KERNEL_PROJECT = 1, DCMESH_KERNEL_CORRECT = 2 };
+int dcmesh_set_tuning(int32_t kernel, int32_t variant);
+int dcmesh_tuning_options(int32_t kernel, int32_t* count);
+
+/* Waits for the events recorded by calls made with DCMESH_FLAG_PROFILE (since
+ * the last collect), and writes per family the summed kernel time in ms and
+ * the number of launches.  total_ms and launches: host arrays of n entries
+ * (n <= DCMESH_N_FAMILIES).  Synchronises with the recorded events. */
+int dcmesh_profile_collect(double* total_ms, int64_t* launches, int32_t n);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* dcmesh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCMESH_H */

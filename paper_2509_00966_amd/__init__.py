@@ -1,0 +1,19 @@
+"""MI355X-native real-time Kohn-Sham step (DC-MESH local field dynamics hot path).
+
+The compute lives in the HIP library ``libdcmesh.so`` (C ABI: include/dcmesh.h);
+this package binds it for torch device tensors.
+"""
+from .api import (  # noqa: F401
+    Domain,
+    Graph,
+    Workspace,
+    adjoint_step,
+    complex_dtype,
+    density,
+    profile_collect,
+    real_dtype,
+    set_tuning,
+    step,
+    tuning_options,
+    workspace_bytes,
+)

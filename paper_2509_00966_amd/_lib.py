@@ -1,0 +1,93 @@
+"""ctypes view of the C ABI in include/dcmesh.h.
+
+Loads the in-tree ``libdcmesh.so`` (built by ``build.py``).  There is no other
+implementation behind these names: if the library is missing the import of
+this module fails.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcmesh.so")
+
+DCMESH_OK = 0
+DCMESH_ERR_INVALID_ARGUMENT = 1
+DCMESH_ERR_UNSUPPORTED = 2
+DCMESH_ERR_WORKSPACE = 3
+DCMESH_ERR_HIP = 4
+DCMESH_ERR_NONFINITE = 5
+
+PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
+FLAG_CHECK_FINITE = 0x1
+FLAG_PROFILE = 0x2
+FAMILIES = ("stencil", "project", "reduce", "correct", "density", "energy", "adjoint", "overlap")
+KERNEL = {"stencil": 0, "project": 1, "correct": 2}
+
+EXPORTS = (
+    "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_density", "dcmesh_adjoint_step",
+    "dcmesh_graph_create", "dcmesh_graph_launch", "dcmesh_graph_destroy",
+    "dcmesh_set_tuning", "dcmesh_tuning_options", "dcmesh_profile_collect", "dcmesh_last_error",
+)
+
+
+class DcmeshDomain(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("fd_order", ctypes.c_int32), ("n_orb", ctypes.c_int32), ("n_proj", ctypes.c_int32),
+        ("h", ctypes.c_double),
+        ("psi", ctypes.c_void_p), ("v_loc", ctypes.c_void_p), ("proj", ctypes.c_void_p),
+        ("d", ctypes.c_void_p), ("occ", ctypes.c_void_p),
+    ]
+
+
+class DcmeshObs(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("j", ctypes.c_void_p), ("energy", ctypes.c_void_p)]
+
+
+class DcmeshDensityOut(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("j", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+                ("hpsi_occ", ctypes.c_void_p), ("overlap", ctypes.c_void_p)]
+
+
+class DcmeshError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dcmesh error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2509_00966_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, D, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                               ctypes.c_double, ctypes.c_size_t)
+    dom_p = ctypes.POINTER(DcmeshDomain)
+    sig = {
+        "dcmesh_workspace_bytes": [dom_p, I32, I32, U32, ctypes.POINTER(SZ)],
+        "dcmesh_step": [dom_p, I32, I32, P, I32, I64, D, I32, ctypes.POINTER(DcmeshObs), P, SZ, U32, P],
+        "dcmesh_density": [dom_p, I32, I32, P, I32, ctypes.POINTER(DcmeshDensityOut), P, SZ, U32, P],
+        "dcmesh_adjoint_step": [dom_p, I32, I32, ctypes.POINTER(P), P, I32, D, P, P, SZ, U32, P],
+        "dcmesh_graph_create": [dom_p, I32, I32, P, I32, I64, D, I32, ctypes.POINTER(DcmeshObs), P, SZ, U32, P,
+                                ctypes.POINTER(P)],
+        "dcmesh_graph_launch": [P, P],
+        "dcmesh_graph_destroy": [P],
+        "dcmesh_set_tuning": [I32, I32],
+        "dcmesh_tuning_options": [I32, ctypes.POINTER(I32)],
+        "dcmesh_profile_collect": [ctypes.POINTER(D), ctypes.POINTER(I64), I32],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.dcmesh_last_error.argtypes = []
+    lib.dcmesh_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def check(code):
+    if code != DCMESH_OK:
+        raise DcmeshError(code, lib.dcmesh_last_error().decode())
+    return code

@@ -1,0 +1,217 @@
+"""Python binding over the C ABI: argument marshalling only.
+
+Every array is a torch tensor on the GPU; the calls pass their data pointers
+and the current HIP stream to the library, which queues all the work.  Nothing
+here computes any part of the step.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import PRECISION, DcmeshDensityOut, DcmeshDomain, DcmeshObs, check, lib
+
+_REAL = {"fp64": torch.float64, "fp32": torch.float32, "split_bf16": torch.float32,
+         "split_fp16": torch.float32}
+_CPLX = {"fp64": torch.complex128, "fp32": torch.complex64, "split_bf16": torch.complex64,
+         "split_fp16": torch.complex64}
+
+
+def real_dtype(precision: str):
+    return _REAL[precision]
+
+
+def complex_dtype(precision: str):
+    return _CPLX[precision]
+
+
+@dataclass
+class Domain:
+    """One periodic domain held in device tensors (layouts as in dcmesh.h)."""
+
+    shape: tuple                  # (nx, ny, nz)
+    fd_order: int
+    h: float
+    psi: torch.Tensor             # [N_g, N_o] complex
+    v_loc: torch.Tensor           # [N_g] real
+    proj: torch.Tensor            # [N_g, N_p] complex
+    d: torch.Tensor               # [N_p] real
+    occ: torch.Tensor             # [N_o] real
+
+    @property
+    def n_grid(self):
+        return self.shape[0] * self.shape[1] * self.shape[2]
+
+    @property
+    def n_orb(self):
+        return self.psi.shape[1]
+
+    @property
+    def n_proj(self):
+        return self.proj.shape[1]
+
+    def check(self, precision: str):
+        cd, rd = _CPLX[precision], _REAL[precision]
+        ng = self.n_grid
+        for name, t, dt, shp in (("psi", self.psi, cd, (ng, self.n_orb)), ("v_loc", self.v_loc, rd, (ng,)),
+                                 ("proj", self.proj, cd, (ng, self.n_proj)), ("d", self.d, rd, (self.n_proj,)),
+                                 ("occ", self.occ, rd, (self.n_orb,))):
+            if t.dtype != dt:
+                raise TypeError(f"{name} must be {dt} for precision {precision}, got {t.dtype}")
+            if tuple(t.shape) != shp:
+                raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shp}")
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+            if not t.is_cuda:
+                raise ValueError(f"{name} must be a GPU tensor")
+
+    def c_struct(self) -> DcmeshDomain:
+        nx, ny, nz = self.shape
+        ptr = lambda t: t.data_ptr() if t.numel() else None
+        return DcmeshDomain(nx, ny, nz, self.fd_order, self.n_orb, self.n_proj, float(self.h),
+                            self.psi.data_ptr(), self.v_loc.data_ptr(), ptr(self.proj), ptr(self.d),
+                            self.occ.data_ptr())
+
+    def with_psi(self, psi: torch.Tensor) -> "Domain":
+        return Domain(self.shape, self.fd_order, self.h, psi, self.v_loc, self.proj, self.d, self.occ)
+
+
+def _doms(domains: Sequence[Domain], precision: str):
+    if precision not in PRECISION:
+        raise ValueError(f"unknown precision {precision}")
+    for d in domains:
+        d.check(precision)
+    arr = (DcmeshDomain * len(domains))(*[d.c_struct() for d in domains])
+    return arr
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_bytes(domains: Sequence[Domain], precision: str) -> int:
+    arr = _doms(domains, precision)
+    out = ctypes.c_size_t(0)
+    check(lib.dcmesh_workspace_bytes(arr, len(domains), PRECISION[precision], 0, ctypes.byref(out)))
+    return out.value
+
+
+class Workspace:
+    """A 256-byte aligned device buffer of at least ``nbytes``."""
+
+    def __init__(self, nbytes: int, device=None):
+        self.raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+        off = (-self.raw.data_ptr()) % 256
+        self.ptr = self.raw.data_ptr() + off
+        self.nbytes = nbytes
+
+    @classmethod
+    def for_domains(cls, domains, precision):
+        return cls(workspace_bytes(domains, precision), domains[0].psi.device)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def step(domains: Sequence[Domain], a: torch.Tensor, dt: float, n_steps: int, precision: str,
+         work: Workspace, obs: Optional[List[dict]] = None, a_per_domain: bool = False,
+         check_finite: bool = False, profile: bool = False, stream=None):
+    """Advance every domain by n_steps Taylor-4 steps.  ``a``: float64 device
+    tensor [n_steps, 3] (or [n_dom, n_steps, 3] with a_per_domain).  ``obs``:
+    optional per-domain dict with 'rho' [n_steps, N_g], 'j' [n_steps, N_g, 3]
+    real tensors and 'energy' [n_steps] float64."""
+    arr = _doms(domains, precision)
+    if a.dtype != torch.float64 or not a.is_contiguous() or not a.is_cuda:
+        raise ValueError("a must be a contiguous float64 GPU tensor")
+    stride = a.shape[-2]
+    o = None
+    if obs is not None:
+        o = (DcmeshObs * len(domains))(*[DcmeshObs(_ptr(x.get("rho")), _ptr(x.get("j")), _ptr(x.get("energy")))
+                                         for x in obs])
+    flags = (_lib.FLAG_CHECK_FINITE if check_finite else 0) | (_lib.FLAG_PROFILE if profile else 0)
+    check(lib.dcmesh_step(arr, len(domains), PRECISION[precision], a.data_ptr(), int(a_per_domain), stride,
+                          float(dt), int(n_steps), o, work.ptr, work.nbytes, flags, _stream(stream)))
+
+
+def density(domains: Sequence[Domain], a: torch.Tensor, precision: str, work: Workspace,
+            outs: List[dict], a_per_domain: bool = False, stream=None):
+    """Observables of the current orbitals.  ``outs``: per-domain dict with any
+    of 'rho', 'j', 'energy' (float64 [1]), 'hpsi_occ', 'overlap' (float64
+    [N_o, N_o, 2])."""
+    arr = _doms(domains, precision)
+    o = (DcmeshDensityOut * len(domains))(*[
+        DcmeshDensityOut(_ptr(x.get("rho")), _ptr(x.get("j")), _ptr(x.get("energy")), _ptr(x.get("hpsi_occ")),
+                         _ptr(x.get("overlap"))) for x in outs])
+    check(lib.dcmesh_density(arr, len(domains), PRECISION[precision], a.data_ptr(), int(a_per_domain), o,
+                             work.ptr, work.nbytes, 0, _stream(stream)))
+
+
+def adjoint_step(domains: Sequence[Domain], lambdas: Sequence[torch.Tensor], a: torch.Tensor, dt: float,
+                 grad: torch.Tensor, precision: str, work: Workspace, a_per_domain: bool = False, stream=None):
+    """lambda <- U^H lambda in place; grad (float64 device, [3] or [n_dom, 3]) += dL/dA."""
+    arr = _doms(domains, precision)
+    cd = _CPLX[precision]
+    for lam, d in zip(lambdas, domains):
+        if lam.dtype != cd or tuple(lam.shape) != tuple(d.psi.shape) or not lam.is_contiguous():
+            raise ValueError("lambda must match psi in dtype, shape and be contiguous")
+    lp = (ctypes.c_void_p * len(lambdas))(*[l.data_ptr() for l in lambdas])
+    check(lib.dcmesh_adjoint_step(arr, len(domains), PRECISION[precision], lp, a.data_ptr(), int(a_per_domain),
+                                  float(dt), grad.data_ptr(), work.ptr, work.nbytes, 0, _stream(stream)))
+
+
+class Graph:
+    """n_steps of ``step`` captured once and replayed with ``launch``."""
+
+    def __init__(self, domains, a, dt, n_steps, precision, work, obs=None, a_per_domain=False, stream=None):
+        arr = _doms(domains, precision)
+        o = None
+        if obs is not None:
+            o = (DcmeshObs * len(domains))(*[DcmeshObs(_ptr(x.get("rho")), _ptr(x.get("j")), _ptr(x.get("energy")))
+                                             for x in obs])
+        self._keep = (domains, a, work, obs)
+        self.handle = ctypes.c_void_p(None)
+        s = stream or torch.cuda.Stream()
+        self.stream = s
+        check(lib.dcmesh_graph_create(arr, len(domains), PRECISION[precision], a.data_ptr(), int(a_per_domain),
+                                      a.shape[-2], float(dt), int(n_steps), o, work.ptr, work.nbytes, 0,
+                                      ctypes.c_void_p(s.cuda_stream), ctypes.byref(self.handle)))
+
+    def launch(self, stream=None):
+        check(lib.dcmesh_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            check(lib.dcmesh_graph_destroy(self.handle))
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile_collect() -> dict:
+    """{family: (total kernel ms, launches)} for calls made with profile=True
+    since the last collect (waits for their events)."""
+    n = len(_lib.FAMILIES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    check(lib.dcmesh_profile_collect(ms, cnt, n))
+    return {f: (ms[i], cnt[i]) for i, f in enumerate(_lib.FAMILIES)}
+
+
+def set_tuning(kernel: str, variant: int):
+    check(lib.dcmesh_set_tuning(_lib.KERNEL[kernel], int(variant)))
+
+
+def tuning_options(kernel: str) -> int:
+    n = ctypes.c_int32(0)
+    check(lib.dcmesh_tuning_options(_lib.KERNEL[kernel], ctypes.byref(n)))
+    return n.value

@@ -1,0 +1,109 @@
+// Shared device-side types for the Kohn-Sham step kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dcm {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;   // four waves per block everywhere
+
+// Buffers a kernel can address through a domain descriptor.
+enum Slot : int {
+  SLOT_PSI = 0,     // caller's orbitals
+  SLOT_B0 = 1,      // workspace psi-sized buffers
+  SLOT_B1 = 2,
+  SLOT_B2 = 3,
+  SLOT_B3 = 4,
+  SLOT_B4 = 5,
+  SLOT_LAMBDA = 6,  // caller's adjoint state
+  SLOT_HPSI = 7,    // caller's f_n H psi_n output
+  SLOT_NONE = 8,
+  N_SLOTS = 8
+};
+
+// One domain as the kernels see it.  Built on the host, copied into the head
+// of the workspace once per call.
+struct DomDesc {
+  int nx, ny, nz, r;            // grid edges, stencil half-width
+  int n_orb, n_proj;
+  long long n_grid;
+  double h;
+  void* slot[N_SLOTS];          // psi-sized complex buffers
+  const void* v;                // [N_g] real
+  const void* proj;             // [N_g][n_proj] complex
+  const void* d;                // [n_proj] real
+  const void* occ;              // [n_orb] real
+  const double* a;              // A samples of this domain, [.][3]
+  long long a_stride;           // doubles between steps (3) -- kept general
+  // workspace (accumulation type of the projector products)
+  void* ppart;                  // [n_split][n_proj][2 n_orb] split-K partials
+  void* pmat;                   // [n_proj][2 n_orb]  P = h^3 B^H u
+  void* qmat;                   // [2 n_proj][2 n_orb] real form of coef D P
+  double* e_loc;                // [n_stencil_items] local-energy partials
+  double* e_nl;                 // [n_reduce_items] nonlocal-energy partials
+  double* g_part;               // [n_grad_items][3] gradient partials
+  int n_split;                  // projection split-K count
+  int split_len;                // grid points per split
+  int zseg;                     // z planes per stencil sweep segment
+  int n_e_loc, n_e_nl, n_g_part;
+  int item0_stencil;            // first item of this domain in its stencil launch
+  int item0_reduce;             // ... in its reduce launch
+  int item0_elem;               // ... in its elementwise launch
+  // per-step observables (may be null)
+  void* rho;                    // [.][N_g]
+  void* jcur;                   // [.][N_g][3]
+  double* energy;               // [.]
+  double* grad;                 // [3] gradient accumulator (adjoint)
+  double* overlap;              // [n_orb][n_orb] complex128
+};
+
+// A unit of work: which domain, and up to three tile coordinates.
+struct Item {
+  int dom, a, b, c;
+};
+
+template <typename T> struct Cplx { T re, im; };
+
+// Central finite-difference weights (second and first derivative), indexed by
+// half-width r = 1..3: c[0] is the centre weight of the second derivative.
+__device__ __forceinline__ double fd2(int r, int m) {
+  // r = 1: (-2, 1); r = 2: (-5/2, 4/3, -1/12); r = 3: (-49/18, 3/2, -3/20, 1/90)
+  if (r == 1) return m == 0 ? -2.0 : 1.0;
+  if (r == 2) return m == 0 ? -2.5 : (m == 1 ? 4.0 / 3.0 : -1.0 / 12.0);
+  return m == 0 ? -49.0 / 18.0 : (m == 1 ? 1.5 : (m == 2 ? -0.15 : 1.0 / 90.0));
+}
+__device__ __forceinline__ double fd1(int r, int m) {
+  // r = 1: (1/2); r = 2: (2/3, -1/12); r = 3: (3/4, -3/20, 1/60)
+  if (r == 1) return 0.5;
+  if (r == 2) return m == 1 ? 2.0 / 3.0 : -1.0 / 12.0;
+  return m == 1 ? 0.75 : (m == 2 ? -0.15 : 1.0 / 60.0);
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sum over a 256-thread block; result valid in thread 0.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) lds4[w] = v;
+  __syncthreads();
+  T s = 0;
+  if (threadIdx.x == 0) s = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+  __syncthreads();
+  return s;
+}
+
+}  // namespace dcm

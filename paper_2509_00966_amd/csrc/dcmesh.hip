@@ -1,0 +1,896 @@
+// Host side of the C ABI declared in include/dcmesh.h: argument validation,
+// workspace layout, work lists, kernel sequencing and graph capture.
+//
+// One call = one "plan": the domain descriptors and the per-kernel work lists
+// are built on the host, copied into the head of the caller's workspace from a
+// pinned staging buffer, and every kernel launch then covers all domains of
+// the call at once (one launch per kernel family and tile variant).
+#include "dcmesh.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "gemm.hpp"
+#include "reduce.hpp"
+#include "stencil.hpp"
+
+using namespace dcm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return fail(DCMESH_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+bool is_fp64(int prec) { return prec == DCMESH_FP64; }
+size_t real_size(int prec) { return is_fp64(prec) ? 8 : 4; }
+
+// ---------------------------------------------------------------------------
+// Tile variants and tuning overrides
+// ---------------------------------------------------------------------------
+struct StencilVariant { int oc, tx, ty; };
+const StencilVariant kStencilF32[] = {{16, 16, 8}, {8, 16, 8}, {16, 8, 8}, {4, 16, 16}};
+const StencilVariant kStencilF64[] = {{8, 16, 8}, {8, 8, 8}, {4, 16, 8}, {16, 8, 4}};
+constexpr int kNStencil = 4;
+
+struct GemmVariant { int bm, bn; };
+const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 64}};
+const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
+constexpr int kNProj = 4;
+const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 128}};
+const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
+constexpr int kNCorr = 4;
+constexpr int kProjKG = 16;
+
+std::atomic<int> g_tune[3] = {{-1}, {-1}, {-1}};
+
+int stencil_variant(const dcmesh_domain&, int) {
+  const int t = g_tune[DCMESH_KERNEL_STENCIL].load();
+  return t >= 0 ? t : 0;
+}
+int proj_variant(const dcmesh_domain& d, int prec) {
+  const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
+  if (t >= 0) return t;
+  if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
+  const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
+  return bigm ? (bign ? 0 : 3) : (bign ? 2 : 1);
+}
+int corr_variant(const dcmesh_domain& d, int prec) {
+  const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
+  if (t >= 0) return t;
+  if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
+  const int n2 = 2 * d.n_orb;
+  return n2 > 128 ? 0 : (n2 > 64 ? 1 : 2);
+}
+
+// ---------------------------------------------------------------------------
+// Validation (host only, before any HIP call)
+// ---------------------------------------------------------------------------
+int validate_domains(const dcmesh_domain* doms, int32_t n_dom, int32_t prec) {
+  if (!doms) return fail(DCMESH_ERR_INVALID_ARGUMENT, "doms is NULL");
+  if (n_dom < 1) return fail(DCMESH_ERR_INVALID_ARGUMENT, "n_dom must be >= 1");
+  if (prec < DCMESH_FP64 || prec > DCMESH_SPLIT_FP16)
+    return fail(DCMESH_ERR_INVALID_ARGUMENT, "unknown precision " + std::to_string(prec));
+  for (int i = 0; i < n_dom; ++i) {
+    const dcmesh_domain& d = doms[i];
+    const std::string at = " (domain " + std::to_string(i) + ")";
+    if (d.fd_order != 2 && d.fd_order != 4 && d.fd_order != 6)
+      return fail(DCMESH_ERR_INVALID_ARGUMENT, "fd_order must be 2, 4 or 6" + at);
+    const int need = d.fd_order + 1;
+    if (d.nx < need || d.ny < need || d.nz < need)
+      return fail(DCMESH_ERR_INVALID_ARGUMENT, "grid edges must be >= fd_order + 1" + at);
+    if ((long long)d.nx * d.ny * d.nz > (1LL << 31))
+      return fail(DCMESH_ERR_INVALID_ARGUMENT, "grid too large (more than 2^31 points)" + at);
+    if (d.n_orb < 1 || d.n_orb > (1 << 16)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "n_orb must be in [1, 65536]" + at);
+    if (d.n_proj < 0 || d.n_proj > (1 << 20)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "n_proj must be in [0, 2^20]" + at);
+    if (!(d.h > 0.0) || !std::isfinite(d.h)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "h must be finite and > 0" + at);
+    if (!d.psi || !d.v_loc || !d.occ) return fail(DCMESH_ERR_INVALID_ARGUMENT, "psi, v_loc and occ are required" + at);
+    if (d.n_proj > 0 && (!d.proj || !d.d)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "proj and d are required when n_proj > 0" + at);
+  }
+  if (prec == DCMESH_SPLIT_BF16 || prec == DCMESH_SPLIT_FP16)
+    return fail(DCMESH_ERR_UNSUPPORTED, "split-precision modes are not available in this build");
+  return DCMESH_OK;
+}
+
+int validate_work(void* work, size_t work_bytes, size_t need) {
+  if (!work) return fail(DCMESH_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(work) % kAlign) return fail(DCMESH_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (work_bytes < need)
+    return fail(DCMESH_ERR_WORKSPACE, "workspace too small: " + std::to_string(work_bytes) + " < " + std::to_string(need));
+  return DCMESH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plans: descriptors, work lists and workspace layout
+// ---------------------------------------------------------------------------
+struct Launch {
+  int variant;       // tile variant of the family
+  size_t first;      // offset (in items) of this launch's list
+  int count;
+};
+
+struct Plan {
+  int prec = 0, n_dom = 0;
+  std::vector<DomDesc> desc;
+  std::vector<Item> items;
+  std::vector<Launch> stencil, proj, reduce, corr, dens, elem, energy, ovl_proj, ovl_reduce;
+  size_t bytes_tables = 0, bytes_total = 0;
+  size_t off_items = 0, off_flag = 0;
+  bool any_proj = false;
+};
+
+// Elements per thread of the elementwise kernels.
+constexpr int kEPT = 4;
+
+void group_launch(std::vector<Launch>& out, std::vector<Item>& items, int n_dom,
+                  const std::function<int(int)>& variant_of,
+                  const std::function<void(int, std::vector<Item>&)>& emit,
+                  const std::function<void(int, int)>& on_first = nullptr) {
+  std::map<int, std::vector<int>> groups;
+  for (int i = 0; i < n_dom; ++i) {
+    const int v = variant_of(i);
+    if (v >= 0) groups[v].push_back(i);
+  }
+  for (auto& kv : groups) {
+    Launch L{kv.first, items.size(), 0};
+    for (int i : kv.second) {
+      if (on_first) on_first(i, (int)(items.size() - L.first));
+      emit(i, items);
+    }
+    L.count = (int)(items.size() - L.first);
+    if (L.count > 0) out.push_back(L);
+  }
+}
+
+// Builds the plan for these domains.  Pointers into the workspace are set when
+// work != nullptr; otherwise only sizes are computed.
+void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* work) {
+  P = Plan();
+  P.prec = prec;
+  P.n_dom = n_dom;
+  P.desc.resize(n_dom);
+  const size_t rs = real_size(prec), cs = 2 * rs;
+  const size_t acc = rs;  // accumulation type of the projector products
+
+  // work lists
+  // stencil launches are keyed by (radius, tile variant): variant + 4 r
+  auto sv = [&](int i) { return stencil_variant(doms[i], prec) + 4 * (doms[i].fd_order / 2); };
+  auto stile = [&](int v) { return is_fp64(prec) ? kStencilF64[v % 4] : kStencilF32[v % 4]; };
+  long long stencil_blocks_xy = 0;
+  for (int i = 0; i < n_dom; ++i) {
+    const StencilVariant t = stile(sv(i));
+    stencil_blocks_xy += cdiv(doms[i].nx, t.tx) * cdiv(doms[i].ny, t.ty) * cdiv(doms[i].n_orb, t.oc);
+  }
+  for (int i = 0; i < n_dom; ++i) {
+    DomDesc& D = P.desc[i];
+    const dcmesh_domain& d = doms[i];
+    std::memset(&D, 0, sizeof(D));
+    D.nx = d.nx; D.ny = d.ny; D.nz = d.nz; D.r = d.fd_order / 2;
+    D.n_orb = d.n_orb; D.n_proj = d.n_proj;
+    D.n_grid = (long long)d.nx * d.ny * d.nz;
+    D.h = d.h;
+    // z segments: aim at >= 1024 stencil blocks in total, segments of >= 16 planes
+    const long long want = std::max<long long>(1, cdiv(1024, std::max<long long>(1, stencil_blocks_xy)));
+    D.zseg = (int)std::min<long long>(d.nz, std::max<long long>(16, cdiv(d.nz, want)));
+    D.split_len = n_dom == 1 ? (int)std::min<long long>(2048, std::max<long long>(256, cdiv(cdiv(D.n_grid, 64), kProjKG) * kProjKG))
+                             : 2048;
+    D.n_split = (int)cdiv(D.n_grid, D.split_len);
+    D.a_stride = 3;
+  }
+  P.any_proj = false;
+  for (int i = 0; i < n_dom; ++i) P.any_proj |= doms[i].n_proj > 0;
+
+  group_launch(P.stencil, P.items, n_dom, sv,
+               [&](int i, std::vector<Item>& it) {
+                 const StencilVariant t = stile(sv(i));
+                 const DomDesc& D = P.desc[i];
+                 const int nzs = (int)cdiv(D.nz, D.zseg), nch = (int)cdiv(D.n_orb, t.oc);
+                 for (int zs = 0; zs < nzs; ++zs)
+                   for (int ch = 0; ch < nch; ++ch)
+                     for (int yt = 0; yt < cdiv(D.ny, t.ty); ++yt)
+                       for (int xt = 0; xt < cdiv(D.nx, t.tx); ++xt) it.push_back({i, xt, yt, (zs << 16) | ch});
+               },
+               [&](int i, int first) { P.desc[i].item0_stencil = first; });
+  for (const Launch& L : P.stencil)
+    for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_e_loc++;
+
+  auto pv = [&](int i) { return doms[i].n_proj > 0 ? proj_variant(doms[i], prec) : -1; };
+  group_launch(P.proj, P.items, n_dom, pv, [&](int i, std::vector<Item>& it) {
+    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i)] : kProjF32[pv(i)];
+    const DomDesc& D = P.desc[i];
+    for (int s = 0; s < D.n_split; ++s)
+      for (int mt = 0; mt < cdiv(D.n_proj, t.bm); ++mt)
+        for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, mt, nt, s});
+  });
+  group_launch(P.reduce, P.items, n_dom, [&](int i) { return doms[i].n_proj > 0 ? 0 : -1; },
+               [&](int i, std::vector<Item>& it) {
+                 const DomDesc& D = P.desc[i];
+                 for (long long b = 0; b < cdiv((long long)D.n_proj * D.n_orb, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
+               },
+               [&](int i, int first) { P.desc[i].item0_reduce = first; });
+  for (const Launch& L : P.reduce)
+    for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_e_nl++;
+  auto cv = [&](int i) { return doms[i].n_proj > 0 ? corr_variant(doms[i], prec) : -1; };
+  group_launch(P.corr, P.items, n_dom, cv, [&](int i, std::vector<Item>& it) {
+    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i)] : kCorrF32[cv(i)];
+    const DomDesc& D = P.desc[i];
+    for (long long gt = 0; gt < cdiv(D.n_grid, t.bm); ++gt)
+      for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, (int)gt, nt, 0});
+  });
+  group_launch(P.dens, P.items, n_dom, [](int) { return 0; }, [&](int i, std::vector<Item>& it) {
+    for (long long b = 0; b < cdiv(P.desc[i].n_grid, 4); ++b) it.push_back({i, (int)b, 0, 0});
+  });
+  group_launch(P.elem, P.items, n_dom, [](int) { return 0; },
+               [&](int i, std::vector<Item>& it) {
+                 const DomDesc& D = P.desc[i];
+                 for (long long b = 0; b < cdiv(D.n_grid * D.n_orb, (long long)kBlock * kEPT); ++b) it.push_back({i, (int)b, 0, 0});
+               },
+               [&](int i, int first) { P.desc[i].item0_elem = first; });
+  for (const Launch& L : P.elem)
+    for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_g_part++;
+  group_launch(P.energy, P.items, n_dom, [](int) { return 0; },
+               [&](int i, std::vector<Item>& it) { it.push_back({i, 0, 0, 0}); });
+  // overlap S = h^3 Psi^H Psi (always FP64 arithmetic)
+  group_launch(P.ovl_proj, P.items, n_dom, [](int) { return 0; }, [&](int i, std::vector<Item>& it) {
+    const DomDesc& D = P.desc[i];
+    for (int s = 0; s < D.n_split; ++s)
+      for (int mt = 0; mt < cdiv(D.n_orb, 64); ++mt)
+        for (int nt = 0; nt < cdiv(2 * D.n_orb, 64); ++nt) it.push_back({i, mt, nt, s});
+  });
+  group_launch(P.ovl_reduce, P.items, n_dom, [](int) { return 0; }, [&](int i, std::vector<Item>& it) {
+    const DomDesc& D = P.desc[i];
+    for (long long b = 0; b < cdiv((long long)D.n_orb * D.n_orb, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
+  });
+
+  // workspace layout
+  size_t off = 0;
+  off += align_up(sizeof(DomDesc) * n_dom);
+  P.off_items = off;
+  off += align_up(sizeof(Item) * P.items.size());
+  P.off_flag = off;
+  off += kAlign;
+  P.bytes_tables = off;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = work ? work + off : nullptr;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return p;
+  };
+  for (int i = 0; i < n_dom; ++i) {
+    DomDesc& D = P.desc[i];
+    const size_t psi_bytes = (size_t)D.n_grid * D.n_orb * cs;
+    for (int s = SLOT_B0; s <= SLOT_B4; ++s) D.slot[s] = take(psi_bytes);
+    const size_t no2 = 2 * (size_t)D.n_orb;
+    const size_t part = std::max((size_t)D.n_split * D.n_proj * no2 * acc, (size_t)D.n_split * D.n_orb * no2 * 8);
+    D.ppart = take(part);
+    D.pmat = take((size_t)D.n_proj * no2 * acc);
+    D.qmat = take(2 * (size_t)D.n_proj * no2 * acc);
+    D.e_loc = (double*)take(sizeof(double) * std::max(1, D.n_e_loc));
+    D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
+    D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
+  }
+  P.bytes_total = off;
+}
+
+// Pinned staging copies of the tables, cached by content so that identical
+// tables never overwrite a buffer that a queued copy may still read.
+struct Staging {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pinned_forever = false;   // referenced by a captured graph
+  ~Staging() {
+    if (done) (void)hipEventDestroy(done);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+std::mutex g_stage_mu;
+std::map<std::pair<size_t, size_t>, std::shared_ptr<Staging>> g_stage;   // (hash, bytes) -> buffer
+
+int stage_tables(const Plan& P, char* work, hipStream_t s, bool capturing, std::shared_ptr<Staging>* keep) {
+  const size_t bytes = P.bytes_tables;
+  std::vector<char> img(bytes, 0);
+  std::memcpy(img.data(), P.desc.data(), sizeof(DomDesc) * P.n_dom);
+  std::memcpy(img.data() + P.off_items, P.items.data(), sizeof(Item) * P.items.size());
+  const size_t hsh = std::hash<std::string>()(std::string(img.data(), img.size()));
+  std::shared_ptr<Staging> st;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    auto itr = g_stage.find({hsh, bytes});
+    if (itr != g_stage.end() && std::memcmp(itr->second->host, img.data(), bytes) == 0) st = itr->second;
+    if (!st) {
+      // drop finished, unreferenced buffers before adding one
+      if (g_stage.size() > 64) {
+        for (auto e = g_stage.begin(); e != g_stage.end();) {
+          if (!e->second->pinned_forever && e->second.use_count() == 1 &&
+              (!e->second->done || hipEventQuery(e->second->done) == hipSuccess))
+            e = g_stage.erase(e);
+          else
+            ++e;
+        }
+      }
+      st = std::make_shared<Staging>();
+      HIPCHK(hipHostMalloc(&st->host, bytes, hipHostMallocDefault));
+      st->bytes = bytes;
+      std::memcpy(st->host, img.data(), bytes);
+      if (!capturing) HIPCHK(hipEventCreateWithFlags(&st->done, hipEventDisableTiming));
+      g_stage[{hsh, bytes}] = st;
+    }
+    if (capturing) st->pinned_forever = true;
+  }
+  HIPCHK(hipMemcpyAsync(work, st->host, bytes, hipMemcpyHostToDevice, s));
+  if (!capturing && st->done) HIPCHK(hipEventRecord(st->done, s));
+  if (keep) *keep = st;
+  return DCMESH_OK;
+}
+
+int check_device() {
+  static std::once_flag once;
+  static int status = DCMESH_OK;
+  static std::string msg;
+  std::call_once(once, [] {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      status = DCMESH_ERR_HIP;
+      msg = "no HIP device";
+      return;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      status = DCMESH_ERR_UNSUPPORTED;
+      msg = std::string("this library is built for gfx950, found ") + prop.gcnArchName;
+    }
+  });
+  return status == DCMESH_OK ? DCMESH_OK : fail(status, msg);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel profiling: HIP events around each launch family (DCMESH_FLAG_PROFILE)
+// ---------------------------------------------------------------------------
+struct ProfRec { int fam; hipEvent_t a, b; };
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
+thread_local bool t_prof_on = false;
+
+hipEvent_t prof_event() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct ProfScope {
+  int fam;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(int f, hipStream_t st) : fam(f), s(st) {
+    if (t_prof_on) {
+      a = prof_event();
+      (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event();
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back({fam, a, b});
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+struct Ctx {
+  const Plan* P;
+  const DomDesc* d_desc;
+  const Item* d_items;
+  hipStream_t s;
+};
+
+template <typename T, int R>
+void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
+  const Item* it = c.d_items + L.first;
+  const dim3 g(L.count), b(kBlock);
+  if constexpr (sizeof(T) == 4) {
+    switch (L.variant) {
+      case 0: k_stencil_sweep<T, R, 16, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      case 1: k_stencil_sweep<T, R, 8, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      case 2: k_stencil_sweep<T, R, 16, 8, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep<T, R, 4, 16, 16><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+    }
+  } else {
+    switch (L.variant) {
+      case 0: k_stencil_sweep<T, R, 8, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      case 1: k_stencil_sweep<T, R, 8, 8, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      case 2: k_stencil_sweep<T, R, 4, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep<T, R, 16, 8, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+    }
+  }
+}
+
+// Stencil launches are keyed by variant + 4 r, so every domain of a launch
+// shares the stencil radius.
+template <typename T>
+void launch_stencil(const Ctx& c, const StencilArgs& a) {
+  ProfScope prof_(DCMESH_FAM_STENCIL, c.s);
+  for (const Launch& L : c.P->stencil) {
+    Launch l2 = L;
+    l2.variant = L.variant % 4;
+    switch (L.variant / 4) {
+      case 1: launch_stencil_r<T, 1>(c, l2, a); break;
+      case 2: launch_stencil_r<T, 2>(c, l2, a); break;
+      default: launch_stencil_r<T, 3>(c, l2, a); break;
+    }
+  }
+}
+
+template <typename T>
+void launch_project(const Ctx& c, int u_slot) {
+  ProfScope prof_(DCMESH_FAM_PROJECT, c.s);
+  ProjArgs a{-1, u_slot, 0};
+  for (const Launch& L : c.P->proj) {
+    const Item* it = c.d_items + L.first;
+    const dim3 g(L.count), b(kBlock);
+    if constexpr (sizeof(T) == 4) {
+      switch (L.variant) {
+        case 0: k_project<T, T, 128, 128, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 1: k_project<T, T, 64, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 2: k_project<T, T, 64, 128, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        default: k_project<T, T, 128, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      }
+    } else {
+      switch (L.variant) {
+        case 0: k_project<T, T, 64, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 1: k_project<T, T, 32, 32, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 2: k_project<T, T, 64, 32, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        default: k_project<T, T, 32, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      }
+    }
+  }
+}
+
+template <typename T>
+void launch_reduce(const Ctx& c, double cre, double cim, int occ_scale, int want_energy) {
+  ProfScope prof_(DCMESH_FAM_REDUCE, c.s);
+  ReduceArgs a{cre, cim, occ_scale, want_energy, 0};
+  for (const Launch& L : c.P->reduce)
+    k_reduce<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
+}
+
+template <typename T>
+void launch_correct(const Ctx& c, int out_slot) {
+  ProfScope prof_(DCMESH_FAM_CORRECT, c.s);
+  for (const Launch& L : c.P->corr) {
+    const Item* it = c.d_items + L.first;
+    const dim3 g(L.count), b(kBlock);
+    if constexpr (sizeof(T) == 4) {
+      switch (L.variant) {
+        case 0: k_correct<T, T, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 1: k_correct<T, T, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 2: k_correct<T, T, 64, 64, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        default: k_correct<T, T, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      }
+    } else {
+      switch (L.variant) {
+        case 0: k_correct<T, T, 64, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 1: k_correct<T, T, 32, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 2: k_correct<T, T, 64, 32, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        default: k_correct<T, T, 32, 32, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      }
+    }
+  }
+}
+
+// out = base + coef * f^occ * H(A_step) u   (full H: local sweep, then the
+// projector correction added in place).
+template <typename T>
+void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double cre, double cim,
+                 int occ_scale, int step, int want_energy) {
+  if (c.P->any_proj) {
+    launch_project<T>(c, u_slot);
+    launch_reduce<T>(c, cre, cim, occ_scale, want_energy);
+  }
+  StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy};
+  launch_stencil<T>(c, sa);
+  if (c.P->any_proj) launch_correct<T>(c, out_slot);
+}
+
+template <typename T>
+void launch_energy(const Ctx& c, int obs) {
+  ProfScope prof_(DCMESH_FAM_ENERGY, c.s);
+  for (const Launch& L : c.P->energy) k_energy_final<<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, obs);
+}
+
+template <typename T>
+void launch_density(const Ctx& c, int step, int obs) {
+  ProfScope prof_(DCMESH_FAM_DENSITY, c.s);
+  for (const Launch& L : c.P->dens) k_density<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, step, obs);
+}
+
+template <typename T>
+void launch_axpy(const Ctx& c, int x_slot, int out_slot) {
+  ProfScope prof_(DCMESH_FAM_ADJOINT, c.s);
+  for (const Launch& L : c.P->elem) k_axpy<T, kEPT><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, x_slot, out_slot);
+}
+
+template <typename T>
+void launch_grad(const Ctx& c, int mu_slot, int u_slot, double cre, double cim) {
+  ProfScope prof_(DCMESH_FAM_ADJOINT, c.s);
+  for (const Launch& L : c.P->elem)
+    k_grad_partial<T, kEPT><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, mu_slot, u_slot, cre, cim);
+}
+
+template <typename T>
+void launch_overlap(const Ctx& c) {
+  ProfScope prof_(DCMESH_FAM_OVERLAP, c.s);
+  ProjArgs a{SLOT_PSI, SLOT_PSI, 1};
+  for (const Launch& L : c.P->ovl_proj)
+    k_project<T, double, 64, 64, kProjKG><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
+  ReduceArgs r{1.0, 0.0, 0, 0, 1};
+  for (const Launch& L : c.P->ovl_reduce) k_reduce<double><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, r);
+}
+
+// ---------------------------------------------------------------------------
+// Entry-point bodies
+// ---------------------------------------------------------------------------
+struct CallSetup {
+  Plan P;
+  Ctx c;
+  std::shared_ptr<Staging> keep;
+};
+
+int prepare(CallSetup& cs, const dcmesh_domain* doms, int32_t n_dom, int32_t prec, void* work,
+            size_t work_bytes, hipStream_t s, uint32_t flags, const std::function<void(Plan&)>& fill) {
+  Plan& P = cs.P;
+  build_plan(P, doms, n_dom, prec, (char*)work);
+  int rc = validate_work(work, work_bytes, P.bytes_total);
+  if (rc) return rc;
+  rc = check_device();
+  if (rc) return rc;
+  fill(P);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(s, &cap));
+  if ((flags & DCMESH_FLAG_PROFILE) && cap != hipStreamCaptureStatusNone)
+    return fail(DCMESH_ERR_INVALID_ARGUMENT, "PROFILE cannot be used under stream capture");
+  t_prof_on = (flags & DCMESH_FLAG_PROFILE) != 0;
+  rc = stage_tables(P, (char*)work, s, cap != hipStreamCaptureStatusNone, &cs.keep);
+  if (rc) return rc;
+  cs.c = Ctx{&P, (const DomDesc*)work, (const Item*)((char*)work + P.off_items), s};
+  return DCMESH_OK;
+}
+
+template <typename T>
+int run_step(CallSetup& cs, int32_t n_steps, double dt, bool want_rho_j, bool want_e) {
+  const Ctx& c = cs.c;
+  for (int k = 0; k < n_steps; ++k) {
+    if (want_rho_j) launch_density<T>(c, k, k);
+    apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0);
+    apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, k, 0);
+    apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B0, 0.0, -dt / 2, 0, k, 0);
+    apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_PSI, 0.0, -dt, 0, k, 0);
+    if (want_e) launch_energy<T>(c, k);
+  }
+  return DCMESH_OK;
+}
+
+int finish(CallSetup& cs, uint32_t flags) {
+  t_prof_on = false;
+  HIPCHK(hipGetLastError());
+  if (flags & DCMESH_FLAG_CHECK_FINITE) {
+    const Ctx& c = cs.c;
+    int* flag = (int*)((char*)c.d_desc + cs.P.off_flag);
+    k_fill_int<<<1, 1, 0, c.s>>>(flag, 0);
+    for (const Launch& L : cs.P.elem) {
+      if (is_fp64(cs.P.prec))
+        k_nonfinite<double, kEPT><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, flag);
+      else
+        k_nonfinite<float, kEPT><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, flag);
+    }
+    int host = 0;
+    HIPCHK(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    HIPCHK(hipStreamSynchronize(c.s));
+    if (host) return fail(DCMESH_ERR_NONFINITE, "psi holds a NaN or Inf after the call");
+  }
+  return DCMESH_OK;
+}
+
+int step_impl(const dcmesh_domain* doms, int32_t n_dom, int32_t prec, const double* a_dev,
+              int32_t a_per_domain, int64_t a_stride, double dt, int32_t n_steps, const dcmesh_obs* obs,
+              void* work, size_t work_bytes, uint32_t flags, hipStream_t s, CallSetup& cs) {
+  int rc = validate_domains(doms, n_dom, prec);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(DCMESH_ERR_INVALID_ARGUMENT, "n_steps must be >= 0");
+  if (n_steps > 0 && !a_dev) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_dev is NULL");
+  if (a_stride < n_steps) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_stride must be >= n_steps");
+  if (!std::isfinite(dt)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "dt must be finite");
+  bool want_rho_j = false, want_e = false;
+  if (obs)
+    for (int i = 0; i < n_dom; ++i) {
+      want_rho_j |= obs[i].rho != nullptr || obs[i].j != nullptr;
+      want_e |= obs[i].energy != nullptr;
+    }
+  rc = prepare(cs, doms, n_dom, prec, work, work_bytes, s, flags, [&](Plan& P) {
+    for (int i = 0; i < n_dom; ++i) {
+      DomDesc& D = P.desc[i];
+      D.slot[SLOT_PSI] = doms[i].psi;
+      D.v = doms[i].v_loc;
+      D.proj = doms[i].proj;
+      D.d = doms[i].d;
+      D.occ = doms[i].occ;
+      D.a = a_dev + (a_per_domain ? (long long)i * a_stride * 3 : 0);
+      if (obs) {
+        D.rho = obs[i].rho;
+        D.jcur = obs[i].j;
+        D.energy = obs[i].energy;
+      }
+    }
+  });
+  if (rc) return rc;
+  if (is_fp64(prec))
+    rc = run_step<double>(cs, n_steps, dt, want_rho_j, want_e);
+  else
+    rc = run_step<float>(cs, n_steps, dt, want_rho_j, want_e);
+  if (rc) return rc;
+  return finish(cs, flags);
+}
+
+struct GraphHandle {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::shared_ptr<Staging> keep;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* dcmesh_last_error(void) { return g_err.c_str(); }
+
+int dcmesh_workspace_bytes(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, uint32_t flags,
+                           size_t* bytes) {
+  (void)flags;
+  if (!bytes) return fail(DCMESH_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  Plan P;
+  build_plan(P, doms, n_dom, precision, nullptr);
+  *bytes = P.bytes_total;
+  return DCMESH_OK;
+}
+
+int dcmesh_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const double* a_dev,
+                int32_t a_per_domain, int64_t a_stride, double dt, int32_t n_steps, const dcmesh_obs* obs,
+                void* work, size_t work_bytes, uint32_t flags, void* stream) {
+  CallSetup cs;
+  return step_impl(doms, n_dom, precision, a_dev, a_per_domain, a_stride, dt, n_steps, obs, work, work_bytes,
+                   flags, (hipStream_t)stream, cs);
+}
+
+int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const double* a_dev,
+                   int32_t a_per_domain, const dcmesh_density_out* out, void* work, size_t work_bytes,
+                   uint32_t flags, void* stream) {
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  if (!a_dev) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_dev is NULL");
+  if (!out) return fail(DCMESH_ERR_INVALID_ARGUMENT, "out is NULL");
+  bool rho_j = false, e = false, hpsi = false, ovl = false;
+  for (int i = 0; i < n_dom; ++i) {
+    rho_j |= out[i].rho || out[i].j;
+    e |= out[i].energy != nullptr;
+    hpsi |= out[i].hpsi_occ != nullptr;
+    ovl |= out[i].overlap != nullptr;
+  }
+  CallSetup cs;
+  hipStream_t s = (hipStream_t)stream;
+  rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
+    for (int i = 0; i < n_dom; ++i) {
+      DomDesc& D = P.desc[i];
+      D.slot[SLOT_PSI] = doms[i].psi;
+      D.slot[SLOT_HPSI] = out[i].hpsi_occ ? out[i].hpsi_occ : D.slot[SLOT_B0];
+      D.v = doms[i].v_loc;
+      D.proj = doms[i].proj;
+      D.d = doms[i].d;
+      D.occ = doms[i].occ;
+      D.a = a_dev + (a_per_domain ? (long long)i * 3 : 0);
+      D.rho = out[i].rho;
+      D.jcur = out[i].j;
+      D.energy = out[i].energy;
+      D.overlap = out[i].overlap;
+    }
+  });
+  if (rc) return rc;
+  const bool f64 = is_fp64(precision);
+  if (rho_j) f64 ? launch_density<double>(cs.c, 0, 0) : launch_density<float>(cs.c, 0, 0);
+  if (e || hpsi) {
+    if (f64) {
+      apply_stage<double>(cs.c, SLOT_PSI, SLOT_NONE, SLOT_HPSI, 1.0, 0.0, 1, 0, e ? 1 : 0);
+      if (e) launch_energy<double>(cs.c, 0);
+    } else {
+      apply_stage<float>(cs.c, SLOT_PSI, SLOT_NONE, SLOT_HPSI, 1.0, 0.0, 1, 0, e ? 1 : 0);
+      if (e) launch_energy<float>(cs.c, 0);
+    }
+  }
+  if (ovl) f64 ? launch_overlap<double>(cs.c) : launch_overlap<float>(cs.c);
+  return finish(cs, flags);
+}
+
+int dcmesh_adjoint_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, void* const* lambda,
+                        const double* a_dev, int32_t a_per_domain, double dt, double* grad_dev, void* work,
+                        size_t work_bytes, uint32_t flags, void* stream) {
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  if (!lambda) return fail(DCMESH_ERR_INVALID_ARGUMENT, "lambda is NULL");
+  for (int i = 0; i < n_dom; ++i)
+    if (!lambda[i]) return fail(DCMESH_ERR_INVALID_ARGUMENT, "lambda[" + std::to_string(i) + "] is NULL");
+  if (!a_dev || !grad_dev) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_dev and grad_dev are required");
+  if (!std::isfinite(dt)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "dt must be finite");
+  CallSetup cs;
+  hipStream_t s = (hipStream_t)stream;
+  rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
+    for (int i = 0; i < n_dom; ++i) {
+      DomDesc& D = P.desc[i];
+      D.slot[SLOT_PSI] = doms[i].psi;
+      D.slot[SLOT_LAMBDA] = lambda[i];
+      D.v = doms[i].v_loc;
+      D.proj = doms[i].proj;
+      D.d = doms[i].d;
+      D.occ = doms[i].occ;
+      D.a = a_dev + (a_per_domain ? (long long)i * 3 : 0);
+      D.grad = grad_dev + (a_per_domain ? (long long)i * 3 : 0);
+    }
+  });
+  if (rc) return rc;
+  auto body = [&](auto tag) {
+    using T = decltype(tag);
+    const Ctx& c = cs.c;
+    // forward Horner intermediates: u3 -> B0, u2 -> B1, u1 -> B2 (u4 = psi)
+    apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, 0, 0);
+    apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, 0, 0);
+    apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B2, 0.0, -dt / 2, 0, 0, 0);
+    // mu_0 = lambda; mu_j = conj(c_j) H mu_{j-1}, added into lambda as soon as
+    // it exists (mu_{j-1} is not needed afterwards); before that,
+    // grad += 2 Re <mu_{j-1}, c_j dH/dA u_j>, c_j = -i dt / j.
+    const int u_of[5] = {-1, SLOT_B2, SLOT_B1, SLOT_B0, SLOT_PSI};
+    const int bufs[2] = {SLOT_B3, SLOT_B4};
+    int mu_prev = SLOT_LAMBDA;
+    for (int j = 1; j <= 4; ++j) {
+      launch_grad<T>(c, mu_prev, u_of[j], 0.0, -dt / j);
+      {
+        ProfScope prof_(DCMESH_FAM_ADJOINT, c.s);
+        k_grad_final<<<a_per_domain ? n_dom : 1, kBlock, 0, c.s>>>(c.d_desc, n_dom, a_per_domain ? 0 : 1);
+      }
+      const int mu_new = bufs[(j - 1) % 2];
+      apply_stage<T>(c, mu_prev, SLOT_NONE, mu_new, 0.0, dt / j, 0, 0, 0);
+      launch_axpy<T>(c, mu_new, SLOT_LAMBDA);
+      mu_prev = mu_new;
+    }
+  };
+  if (is_fp64(precision))
+    body(double());
+  else
+    body(float());
+  return finish(cs, flags);
+}
+
+int dcmesh_graph_create(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const double* a_dev,
+                        int32_t a_per_domain, int64_t a_stride, double dt, int32_t n_steps, const dcmesh_obs* obs,
+                        void* work, size_t work_bytes, uint32_t flags, void* stream, void** graph_out) {
+  if (!graph_out) return fail(DCMESH_ERR_INVALID_ARGUMENT, "graph_out is NULL");
+  if (flags & DCMESH_FLAG_CHECK_FINITE)
+    return fail(DCMESH_ERR_INVALID_ARGUMENT, "CHECK_FINITE cannot be captured into a graph");
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<GraphHandle> g(new GraphHandle());
+  CallSetup cs;
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  rc = step_impl(doms, n_dom, precision, a_dev, a_per_domain, a_stride, dt, n_steps, obs, work, work_bytes, flags,
+                 s, cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(DCMESH_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  g->graph = graph;
+  HIPCHK(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+  g->keep = cs.keep;
+  *graph_out = g.release();
+  return DCMESH_OK;
+}
+
+int dcmesh_graph_launch(void* graph, void* stream) {
+  if (!graph) return fail(DCMESH_ERR_INVALID_ARGUMENT, "graph is NULL");
+  GraphHandle* g = (GraphHandle*)graph;
+  HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return DCMESH_OK;
+}
+
+int dcmesh_graph_destroy(void* graph) {
+  if (!graph) return fail(DCMESH_ERR_INVALID_ARGUMENT, "graph is NULL");
+  GraphHandle* g = (GraphHandle*)graph;
+  if (g->exec) HIPCHK(hipGraphExecDestroy(g->exec));
+  if (g->graph) HIPCHK(hipGraphDestroy(g->graph));
+  delete g;
+  return DCMESH_OK;
+}
+
+int dcmesh_profile_collect(double* total_ms, int64_t* launches, int32_t n) {
+  if (!total_ms || !launches || n < 0 || n > DCMESH_N_FAMILIES)
+    return fail(DCMESH_ERR_INVALID_ARGUMENT, "bad profile buffers");
+  for (int i = 0; i < n; ++i) { total_ms[i] = 0; launches[i] = 0; }
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  int rc = DCMESH_OK;
+  for (const ProfRec& r : recs) {
+    float ms = 0;
+    if (rc == DCMESH_OK) {
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e != hipSuccess) rc = fail(DCMESH_ERR_HIP, std::string("profile events: ") + hipGetErrorString(e));
+    }
+    if (r.fam < n) { total_ms[r.fam] += ms; launches[r.fam] += 1; }
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (const ProfRec& r : recs) { g_prof_pool.push_back(r.a); g_prof_pool.push_back(r.b); }
+  return rc;
+}
+
+int dcmesh_set_tuning(int32_t kernel, int32_t variant) {
+  int count = 0;
+  int rc = dcmesh_tuning_options(kernel, &count);
+  if (rc) return rc;
+  if (variant < -1 || variant >= count) return fail(DCMESH_ERR_INVALID_ARGUMENT, "variant out of range");
+  g_tune[kernel].store(variant);
+  return DCMESH_OK;
+}
+
+int dcmesh_tuning_options(int32_t kernel, int32_t* count) {
+  if (!count) return fail(DCMESH_ERR_INVALID_ARGUMENT, "count is NULL");
+  switch (kernel) {
+    case DCMESH_KERNEL_STENCIL: *count = kNStencil; return DCMESH_OK;
+    case DCMESH_KERNEL_PROJECT: *count = kNProj; return DCMESH_OK;
+    case DCMESH_KERNEL_CORRECT: *count = kNCorr; return DCMESH_OK;
+    default: return fail(DCMESH_ERR_INVALID_ARGUMENT, "unknown kernel family");
+  }
+}
+
+}  // extern "C"

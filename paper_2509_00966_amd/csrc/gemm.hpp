@@ -1,0 +1,252 @@
+// Projector products of the nonlocal term (Sec. V.B.5) on the matrix cores.
+//
+//   projection  P = h^3 B^H u        M = n_proj, N = n_orb, K = N_g   (split-K)
+//   correction  out += B Q            M = N_g,   N = n_orb, K = n_proj
+//
+// Complex products are written as one real product on the interleaved
+// (re, im) storage, so both operands are read straight from the complex arrays:
+//   projection: rows p, columns j = (n, c), reduction index (g, c'):
+//       A[p][(g,0)] = Re B[g][p], A[p][(g,1)] = Im B[g][p]
+//       X[(g,0)][j] = u_raw[g][j],  X[(g,1)][(n,0)] = Im u, X[(g,1)][(n,1)] = -Re u
+//   giving Re/Im of sum_g conj(B) u in columns (n,0)/(n,1);
+//   correction: out_raw[g][j] += sum_k B_raw[g][k] Q'[k][j] with the real form
+//       Q'[(p,0)][(n,0)] = Re Q, Q'[(p,1)][(n,0)] = -Im Q,
+//       Q'[(p,0)][(n,1)] = Im Q, Q'[(p,1)][(n,1)] = Re Q.
+// A complex product therefore costs 8 M N K real flops, all on MFMA.
+//
+// MFMA shape: 16x16x4 (FP32 and FP64 share the lane layout): operand lane l
+// holds row/column l % 16 and reduction index l / 16; the accumulator lane l
+// holds column l % 16, rows 4 (l / 16) + i, i = 0..3.
+#pragma once
+
+#include "common.hpp"
+
+namespace dcm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename TC> struct Mfma;
+template <> struct Mfma<float> {
+  using acc_t = f32x4;
+  __device__ __forceinline__ static acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  using acc_t = f64x4;
+  __device__ __forceinline__ static acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+struct ProjArgs {
+  int a_slot;        // -1: the projectors B; else a psi-sized slot (overlap)
+  int u_slot;        // right operand
+  int out_overlap;   // write partials to the same ppart buffer either way
+};
+
+// Items: (dom, p tile, j tile, split).  Block = 4 waves in 2 x 2, each wave a
+// (BM/2) x (BN/2) tile of 16 x 16 MFMA blocks.  KG grid points per LDS stage.
+template <typename TIn, typename TC, int BM, int BN, int KG>
+__global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ doms,
+                                                    const Item* __restrict__ items, ProjArgs args) {
+  constexpr int TM = BM / 32, TN = BN / 32;
+  constexpr int LA = 2 * BM + 4, LB = BN + 4;          // padded LDS rows
+  __shared__ TC sA[KG * LA];
+  __shared__ TC sB[KG * LB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = args.a_slot < 0 ? D.n_proj : D.n_orb;
+  const int no2 = 2 * D.n_orb;
+  const TIn* __restrict__ Bsrc = args.a_slot < 0 ? (const TIn*)D.proj : (const TIn*)D.slot[args.a_slot];
+  const TIn* __restrict__ U = (const TIn*)D.slot[args.u_slot];
+  const int p0 = it.a * BM, j0 = it.b * BN;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BN / 2);
+  using acc_t = typename Mfma<TC>::acc_t;
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  const int ll = lane % 16, lk = lane / 16;
+  for (long long gc = g_begin; gc < g_end; gc += KG) {
+    for (int idx = threadIdx.x; idx < KG * 2 * BM; idx += kBlock) {
+      const int gl = idx / (2 * BM), c = idx % (2 * BM);
+      const long long g = gc + gl;
+      const int p2 = 2 * p0 + c;
+      sA[gl * LA + c] = (g < g_end && p2 < 2 * np) ? (TC)Bsrc[g * (2 * np) + p2] : (TC)0;
+    }
+    for (int idx = threadIdx.x; idx < KG * BN; idx += kBlock) {
+      const int gl = idx / BN, c = idx % BN;
+      const long long g = gc + gl;
+      const int j = j0 + c;
+      sB[gl * LB + c] = (g < g_end && j < no2) ? (TC)U[g * no2 + j] : (TC)0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < KG / 2; ++ks) {
+      const int gl = 2 * ks + (lk >> 1), cc = lk & 1;
+      TC a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = sA[gl * LA + 2 * (wm0 + i * 16 + ll) + cc];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = wn0 + j * 16 + ll;
+        b[j] = cc == 0 ? sB[gl * LB + col] : ((col & 1) == 0 ? sB[gl * LB + col + 1] : -sB[gl * LB + col - 1]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<TC>::run(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  TC* __restrict__ part = (TC*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (p < np && jj < no2) part[(long long)p * no2 + jj] = acc[i][j][r];
+      }
+}
+
+struct ReduceArgs {
+  double cre, cim;     // coef folded into Q = coef D P (f^s)
+  int occ_scale;       // fold f_n into Q
+  int want_energy;     // nonlocal energy partials sum f D |P|^2
+  int write_overlap;   // overlap mode: write h^3 * sum to D.overlap (complex128)
+};
+
+// Items: (dom, block index over n_proj * n_orb pairs).  Deterministic: the
+// split-K partials are summed in split order.
+template <typename TC>
+__global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ doms,
+                                                   const Item* __restrict__ items, ReduceArgs args) {
+  __shared__ double red[4];
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = args.write_overlap ? D.n_orb : D.n_proj;
+  const int no = D.n_orb, no2 = 2 * no;
+  const long long idx = (long long)it.a * kBlock + threadIdx.x;
+  const bool ok = idx < (long long)np * no;
+  double e = 0.0;
+  if (ok) {
+    const int p = (int)(idx / no), n = (int)(idx % no);
+    const TC* part = (const TC*)D.ppart;
+    const long long stride = (long long)np * no2;
+    TC sr = 0, si = 0;
+    for (int s = 0; s < D.n_split; ++s) {
+      sr += part[s * stride + (long long)p * no2 + 2 * n];
+      si += part[s * stride + (long long)p * no2 + 2 * n + 1];
+    }
+    const double h3 = D.h * D.h * D.h;
+    if (args.write_overlap) {
+      D.overlap[((long long)p * no + n) * 2] = h3 * (double)sr;
+      D.overlap[((long long)p * no + n) * 2 + 1] = h3 * (double)si;
+    } else {
+      const TC pr = (TC)(h3 * (double)sr), pi = (TC)(h3 * (double)si);
+      TC* P = (TC*)D.pmat;
+      P[(long long)p * no2 + 2 * n] = pr;
+      P[(long long)p * no2 + 2 * n + 1] = pi;
+      const TC dp = ((const TC*)D.d)[p];
+      const TC fn = ((const TC*)D.occ)[n];
+      const TC sc = args.occ_scale ? dp * fn : dp;
+      const TC qr = sc * ((TC)args.cre * pr - (TC)args.cim * pi);
+      const TC qi = sc * ((TC)args.cre * pi + (TC)args.cim * pr);
+      TC* Q = (TC*)D.qmat;
+      Q[(long long)(2 * p) * no2 + 2 * n] = qr;
+      Q[(long long)(2 * p) * no2 + 2 * n + 1] = qi;
+      Q[(long long)(2 * p + 1) * no2 + 2 * n] = -qi;
+      Q[(long long)(2 * p + 1) * no2 + 2 * n + 1] = qr;
+      if (args.want_energy) e = (double)fn * (double)dp * ((double)pr * pr + (double)pi * pi);
+    }
+  }
+  if (args.want_energy) {
+    const double s = block_sum(e, red);
+    if (threadIdx.x == 0) D.e_nl[blockIdx.x - D.item0_reduce] = s;
+  }
+}
+
+// Items: (dom, g tile, j tile).  out_raw[g][j] += sum_k B_raw[g][k] Q'[k][j].
+// Block = 4 waves in 2 x 2; KC real reduction indices per LDS stage.
+template <typename TIn, typename TC, int BMG, int BN, int KC>
+__global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ doms,
+                                                    const Item* __restrict__ items, int out_slot) {
+  constexpr int TM = BMG / 32, TN = BN / 32;
+  constexpr int LA = KC + 1, LB = BN + 4;
+  __shared__ TC sA[BMG * LA];
+  __shared__ TC sB[KC * LB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int K = 2 * D.n_proj, no2 = 2 * D.n_orb;
+  const long long g0 = (long long)it.a * BMG;
+  const int j0 = it.b * BN;
+  const TIn* __restrict__ Braw = (const TIn*)D.proj;
+  const TC* __restrict__ Q = (const TC*)D.qmat;
+  TIn* __restrict__ out = (TIn*)D.slot[out_slot];
+
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wm0 = (wv / 2) * (BMG / 2), wn0 = (wv % 2) * (BN / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  using acc_t = typename Mfma<TC>::acc_t;
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int idx = threadIdx.x; idx < BMG * KC; idx += kBlock) {
+      const int r = idx / KC, c = idx % KC;
+      const long long g = g0 + r;
+      const int k = k0 + c;
+      sA[r * LA + c] = (g < D.n_grid && k < K) ? (TC)Braw[g * K + k] : (TC)0;
+    }
+    for (int idx = threadIdx.x; idx < KC * BN; idx += kBlock) {
+      const int r = idx / BN, c = idx % BN;
+      const int k = k0 + r, j = j0 + c;
+      sB[r * LB + c] = (k < K && j < no2) ? Q[(long long)k * no2 + j] : (TC)0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      TC a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = sA[(wm0 + i * 16 + ll) * LA + ks * 4 + lk];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = sB[(ks * 4 + lk) * LB + wn0 + j * 16 + ll];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<TC>::run(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && jj < no2) {
+          TIn* o = out + g * no2 + jj;
+          *o = (TIn)((TC)*o + acc[i][j][r]);
+        }
+      }
+}
+
+}  // namespace dcm

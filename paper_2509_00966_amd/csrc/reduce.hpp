@@ -1,0 +1,197 @@
+// Reductions over orbitals and over the grid: density and local current,
+// energy finalisation, the gradient inner products of the adjoint step, and
+// small elementwise helpers.  Orbital reductions give one wave per grid point
+// (lanes over orbitals, wave shuffles to combine); grid reductions write one
+// FP64 partial per block and are finished in a fixed order, so every result is
+// bitwise reproducible.
+#pragma once
+
+#include "common.hpp"
+
+namespace dcm {
+
+// rho = sum_n f_n |psi_n|^2, j_d = sum_n f_n [Im(conj psi_n D1_d psi_n) + A_d |psi_n|^2].
+// Items: (dom, block of 4 grid points).  step: A sample; obs: output row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_density(const DomDesc* __restrict__ doms,
+                                                    const Item* __restrict__ items, int step, int obs) {
+  using C = Cplx<T>;
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const long long g = (long long)it.a * 4 + threadIdx.x / kWave;
+  if (g >= D.n_grid) return;
+  const int lane = threadIdx.x % kWave;
+  const int nx = D.nx, ny = D.ny, nz = D.nz, no = D.n_orb, r = D.r;
+  const int x = (int)(g % nx), y = (int)((g / nx) % ny), z = (int)(g / ((long long)nx * ny));
+  const C* __restrict__ psi = (const C*)D.slot[SLOT_PSI];
+  const T* __restrict__ occ = (const T*)D.occ;
+  const double ih = 1.0 / D.h;
+  double rho = 0, j0 = 0, j1 = 0, j2 = 0;
+  for (int n = lane; n < no; n += kWave) {
+    const double f = (double)occ[n];
+    const C c = psi[g * no + n];
+    rho += f * ((double)c.re * c.re + (double)c.im * c.im);
+    double jd[3] = {0, 0, 0};
+    for (int m = 1; m <= r; ++m) {
+      const double am = fd1(r, m) * ih;
+      const long long gxp = ((long long)z * ny + y) * nx + wrap(x + m, nx);
+      const long long gxm = ((long long)z * ny + y) * nx + wrap(x - m, nx);
+      const long long gyp = ((long long)z * ny + wrap(y + m, ny)) * nx + x;
+      const long long gym = ((long long)z * ny + wrap(y - m, ny)) * nx + x;
+      const long long gzp = ((long long)wrap(z + m, nz) * ny + y) * nx + x;
+      const long long gzm = ((long long)wrap(z - m, nz) * ny + y) * nx + x;
+      const long long nb[3][2] = {{gxp, gxm}, {gyp, gym}, {gzp, gzm}};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const C up = psi[nb[d][0] * no + n], um = psi[nb[d][1] * no + n];
+        const double tr = (double)up.re - um.re, ti = (double)up.im - um.im;
+        // Im(conj(c) * t) = c.re t.im - c.im t.re
+        jd[d] += am * ((double)c.re * ti - (double)c.im * tr);
+      }
+    }
+    j0 += f * jd[0];
+    j1 += f * jd[1];
+    j2 += f * jd[2];
+  }
+  rho = wave_sum(rho);
+  j0 = wave_sum(j0);
+  j1 = wave_sum(j1);
+  j2 = wave_sum(j2);
+  if (lane == 0) {
+    const double* A = D.a + (long long)step * D.a_stride;
+    if (D.rho) ((T*)D.rho)[(long long)obs * D.n_grid + g] = (T)rho;
+    if (D.jcur) {
+      T* j = (T*)D.jcur + ((long long)obs * D.n_grid + g) * 3;
+      j[0] = (T)(j0 + A[0] * rho);
+      j[1] = (T)(j1 + A[1] * rho);
+      j[2] = (T)(j2 + A[2] * rho);
+    }
+  }
+}
+
+// energy[obs] = h^3 sum(e_loc) + sum(e_nl).  Items: (dom); one block per domain.
+__global__ __launch_bounds__(kBlock) void k_energy_final(const DomDesc* __restrict__ doms,
+                                                         const Item* __restrict__ items, int obs) {
+  __shared__ double red[4];
+  const DomDesc& D = doms[items[blockIdx.x].dom];
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < D.n_e_loc; i += kBlock) a += D.e_loc[i];
+  for (int i = threadIdx.x; i < D.n_e_nl; i += kBlock) b += D.e_nl[i];
+  const double sa = block_sum(a, red);
+  const double sb = block_sum(b, red);
+  if (threadIdx.x == 0 && D.energy) D.energy[obs] = D.h * D.h * D.h * sa + sb;
+}
+
+// Gradient partials: for each d, sum Re(conj(mu) * coef * (-i D1_d u + A_d u)).
+// Items: (dom, element block); EPT elements per thread.
+template <typename T, int EPT>
+__global__ __launch_bounds__(kBlock) void k_grad_partial(const DomDesc* __restrict__ doms,
+                                                         const Item* __restrict__ items, int mu_slot,
+                                                         int u_slot, double cre, double cim) {
+  using C = Cplx<T>;
+  __shared__ double red[4];
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int nx = D.nx, ny = D.ny, nz = D.nz, no = D.n_orb, r = D.r;
+  const long long total = D.n_grid * no;
+  const C* __restrict__ mu = (const C*)D.slot[mu_slot];
+  const C* __restrict__ u = (const C*)D.slot[u_slot];
+  const double* A = D.a;
+  const double ih = 1.0 / D.h;
+  double acc[3] = {0, 0, 0};
+  for (int i = 0; i < EPT; ++i) {
+    const long long e = ((long long)it.a * EPT + i) * kBlock + threadIdx.x;
+    if (e >= total) break;
+    const long long g = e / no;
+    const int n = (int)(e - g * no);
+    const int x = (int)(g % nx), y = (int)((g / nx) % ny), z = (int)(g / ((long long)nx * ny));
+    const C m = mu[e], c = u[e];
+    // w = conj(mu) * coef
+    const double wr = (double)m.re * cre + (double)m.im * cim;
+    const double wi = (double)m.re * cim - (double)m.im * cre;
+    for (int d = 0; d < 3; ++d) {
+      double dr = 0, di = 0;
+      for (int k = 1; k <= r; ++k) {
+        long long gp, gm;
+        if (d == 0) {
+          gp = ((long long)z * ny + y) * nx + wrap(x + k, nx);
+          gm = ((long long)z * ny + y) * nx + wrap(x - k, nx);
+        } else if (d == 1) {
+          gp = ((long long)z * ny + wrap(y + k, ny)) * nx + x;
+          gm = ((long long)z * ny + wrap(y - k, ny)) * nx + x;
+        } else {
+          gp = ((long long)wrap(z + k, nz) * ny + y) * nx + x;
+          gm = ((long long)wrap(z - k, nz) * ny + y) * nx + x;
+        }
+        const C up = u[gp * no + n], um = u[gm * no + n];
+        const double ak = fd1(r, k) * ih;
+        dr += ak * ((double)up.re - um.re);
+        di += ak * ((double)up.im - um.im);
+      }
+      // t = -i D1 u + A_d u
+      const double tr = di + A[d] * c.re;
+      const double ti = -dr + A[d] * c.im;
+      acc[d] += wr * tr - wi * ti;
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    const double s = block_sum(acc[d], red);
+    if (threadIdx.x == 0) D.g_part[(long long)(blockIdx.x - D.item0_elem) * 3 + d] = s;
+  }
+}
+
+// grad[d] += 2 h^3 sum(partials).  When the field is shared (one gradient for
+// all domains) a single block walks every domain in order.
+__global__ __launch_bounds__(kBlock) void k_grad_final(const DomDesc* __restrict__ doms, int n_dom,
+                                                       int shared) {
+  __shared__ double red[4];
+  const int d0 = shared ? 0 : blockIdx.x, d1 = shared ? n_dom : blockIdx.x + 1;
+  double s[3] = {0, 0, 0};
+  for (int dm = d0; dm < d1; ++dm) {
+    const DomDesc& D = doms[dm];
+    double a[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < D.n_g_part; i += kBlock)
+      for (int d = 0; d < 3; ++d) a[d] += D.g_part[(long long)i * 3 + d];
+    const double h3 = D.h * D.h * D.h;
+    for (int d = 0; d < 3; ++d) s[d] += 2.0 * h3 * block_sum(a[d], red);
+  }
+  if (threadIdx.x == 0) {
+    double* g = doms[d0].grad;
+    for (int d = 0; d < 3; ++d) g[d] += s[d];
+  }
+}
+
+// out += x over psi-sized slots.  Items: (dom, element block).
+template <typename T, int EPT>
+__global__ __launch_bounds__(kBlock) void k_axpy(const DomDesc* __restrict__ doms,
+                                                 const Item* __restrict__ items, int x_slot, int out_slot) {
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const long long total = D.n_grid * D.n_orb * 2;
+  const T* __restrict__ x = (const T*)D.slot[x_slot];
+  T* __restrict__ out = (T*)D.slot[out_slot];
+  for (int i = 0; i < 2 * EPT; ++i) {
+    const long long e = ((long long)it.a * 2 * EPT + i) * kBlock + threadIdx.x;
+    if (e < total) out[e] += x[e];
+  }
+}
+
+// Sets *flag to 1 if any value of the psi slot is not finite.
+template <typename T, int EPT>
+__global__ __launch_bounds__(kBlock) void k_nonfinite(const DomDesc* __restrict__ doms,
+                                                      const Item* __restrict__ items, int* flag) {
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const long long total = D.n_grid * D.n_orb * 2;
+  const T* __restrict__ x = (const T*)D.slot[SLOT_PSI];
+  int bad = 0;
+  for (int i = 0; i < 2 * EPT; ++i) {
+    const long long e = ((long long)it.a * 2 * EPT + i) * kBlock + threadIdx.x;
+    if (e < total && !isfinite(x[e])) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void k_fill_int(int* p, int v) { *p = v; }
+
+}  // namespace dcm

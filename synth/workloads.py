@@ -130,33 +130,39 @@ def _gauss3(shape, h, c, s) -> np.ndarray:
 
 
 def _orbitals(shape, h, centres, widths, phases) -> np.ndarray:
-    """psi_n = sum_i exp(i phi_ni) G(r; c_ni, s_ni), built per orbital as a
-    small matrix product over the 8 separable terms."""
+    """psi_n = sum_i exp(i phi_ni) G(r; c_ni, s_ni), assembled plane by plane:
+    psi[z][(y, x), n] = sum_i (fy (x) fx)_ni[(y, x)] * exp(i phi_ni) fz_ni[z]."""
     nx, ny, nz = shape
     n_orb, n_g = centres.shape[0], centres.shape[1]
-    out = np.empty((n_orb, nx * ny * nz), dtype=np.complex128)       # [N_o, N_g]
+    fx = np.empty((n_orb, n_g, nx))
+    fy = np.empty((n_orb, n_g, ny))
+    fz = np.empty((n_orb, n_g, nz))
     for n in range(n_orb):
-        fx = np.stack([_axis_factor(nx, h, centres[n, i, 0], widths[n, i], False) for i in range(n_g)])
-        fy = np.stack([_axis_factor(ny, h, centres[n, i, 1], widths[n, i], False) for i in range(n_g)])
-        fz = np.stack([_axis_factor(nz, h, centres[n, i, 2], widths[n, i], False) for i in range(n_g)])
-        zy = (np.exp(1j * phases[n])[:, None, None] * fz[:, :, None] * fy[:, None, :]).reshape(n_g, nz * ny)
-        out[n] = (zy.T @ fx).reshape(-1)
-    return np.ascontiguousarray(out.T)
+        for i in range(n_g):
+            fx[n, i] = _axis_factor(nx, h, centres[n, i, 0], widths[n, i], False)
+            fy[n, i] = _axis_factor(ny, h, centres[n, i, 1], widths[n, i], False)
+            fz[n, i] = _axis_factor(nz, h, centres[n, i, 2], widths[n, i], False)
+    yx = (fy[:, :, :, None] * fx[:, :, None, :]).reshape(n_orb, n_g, ny * nx)      # [N_o, 8, yx]
+    wz = np.exp(1j * phases)[:, :, None] * fz                                       # [N_o, 8, nz]
+    out = np.empty((nz, ny * nx, n_orb), dtype=np.complex128)
+    for z in range(nz):
+        out[z] = np.einsum("niy,ni->yn", yx, wz[:, :, z])
+    return out.reshape(nz * ny * nx, n_orb)
 
 
 def _orthonormalise(psi: np.ndarray, h: float) -> np.ndarray:
     """Cholesky-QR: Psi <- Psi R^-1 with R^H R = h^3 Psi^H Psi."""
     s = h ** 3 * (psi.conj().T @ psi)
     r = np.linalg.cholesky(s).conj().T          # upper, R^H R = S
-    return np.linalg.solve(r.T, psi.T).T        # psi @ inv(R)
+    return psi @ np.linalg.inv(r)
 
 
 def _projectors(shape, h, atoms, per_atom, phases) -> np.ndarray:
+    """Columns s, p_x, p_y, p_z per atom and radius, assembled plane by plane
+    from their separable factors, normalised and phased."""
     nx, ny, nz = shape
     radii = PROJ_RADII[:1] if per_atom == 4 else PROJ_RADII
-    n_g = nx * ny * nz
-    bt = np.empty((len(atoms) * 4 * len(radii), n_g), dtype=np.complex128)   # [N_p, N_g]
-    col = 0
+    fxs, fys, fzs = [], [], []
     for c in atoms:
         for rc in radii:
             gx = _axis_factor(nx, h, c[0], rc, False)
@@ -166,11 +172,17 @@ def _projectors(shape, h, atoms, per_atom, phases) -> np.ndarray:
             ly = _axis_factor(ny, h, c[1], rc, True)
             lz = _axis_factor(nz, h, c[2], rc, True)
             for fz, fy, fx in ((gz, gy, gx), (gz, gy, lx), (gz, ly, gx), (lz, gy, gx)):  # s, px, py, pz
-                f = _outer3(fz, fy, fx)
-                norm = np.sqrt(h ** 3 * np.dot(f, f))
-                bt[col] = f * (np.exp(1j * phases[col]) / norm)
-                col += 1
-    return np.ascontiguousarray(bt.T)
+                fxs.append(fx)
+                fys.append(fy)
+                fzs.append(fz)
+    fx, fy, fz = np.array(fxs), np.array(fys), np.array(fzs)                      # [N_p, n]
+    norms = np.sqrt(h ** 3 * np.sum(fx ** 2, 1) * np.sum(fy ** 2, 1) * np.sum(fz ** 2, 1))
+    scale = np.exp(1j * np.asarray(phases)) / norms
+    yx = np.ascontiguousarray((fy[:, :, None] * fx[:, None, :]).reshape(len(fx), ny * nx).T)   # [yx, N_p]
+    out = np.empty((nz, ny * nx, len(fx)), dtype=np.complex128)
+    for z in range(nz):
+        np.multiply(yx, (fz[:, z] * scale)[None, :], out=out[z])
+    return out.reshape(nz * ny * nx, len(fx))
 
 
 def make_domain(seed, shape: Sequence[int], n_orb: int, n_atoms: int,

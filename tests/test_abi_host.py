@@ -1,0 +1,116 @@
+"""The C-ABI library loads, exports every entry point declared in
+include/dcmesh.h, and rejects invalid arguments on the host (no GPU needed:
+validation happens before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2509_00966_amd import _lib
+    return _lib
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    header = open(os.path.join(ROOT, "include", "dcmesh.h")).read()
+    declared = set(re.findall(r"\b(?:int|const char\*)\s+(dcmesh_\w+)\s*\(", header))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(L.lib, name)
+
+
+def _dom(L, **kw):
+    fake = 0x10000
+    d = dict(nx=10, ny=10, nz=10, fd_order=6, n_orb=4, n_proj=2, h=0.4, psi=fake, v_loc=fake,
+             proj=fake, d=fake, occ=fake)
+    d.update(kw)
+    return (L.DcmeshDomain * 1)(L.DcmeshDomain(**d))
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(fd_order=5), 1),
+    (dict(nx=6), 1),                 # < fd_order + 1
+    (dict(n_orb=0), 1),
+    (dict(n_proj=-1), 1),
+    (dict(h=0.0), 1),
+    (dict(h=float("nan")), 1),
+    (dict(psi=None), 1),
+    (dict(proj=None), 1),
+    (dict(proj=None, d=None, n_proj=0), 0),
+])
+def test_workspace_bytes_validation(kw, code):
+    L = _lib()
+    out = ctypes.c_size_t(0)
+    rc = L.lib.dcmesh_workspace_bytes(_dom(L, **kw), 1, 1, 0, ctypes.byref(out))
+    assert rc == code, L.lib.dcmesh_last_error()
+    if code == 0:
+        assert out.value > 10 * 10 * 10 * 4 * 8 * 2     # at least two psi-sized buffers
+
+
+def test_bad_precision_and_counts():
+    L = _lib()
+    out = ctypes.c_size_t(0)
+    assert L.lib.dcmesh_workspace_bytes(_dom(L), 1, 7, 0, ctypes.byref(out)) == 1
+    assert L.lib.dcmesh_workspace_bytes(_dom(L), 0, 1, 0, ctypes.byref(out)) == 1
+    assert L.lib.dcmesh_workspace_bytes(None, 1, 1, 0, ctypes.byref(out)) == 1
+    assert L.lib.dcmesh_workspace_bytes(_dom(L), 1, 1, 0, None) == 1
+    assert b"NULL" in L.lib.dcmesh_last_error()
+
+
+def test_step_rejects_missing_or_small_workspace_before_touching_the_gpu():
+    L = _lib()
+    d = _dom(L)
+    fake = ctypes.c_void_p(0x10000)
+    rc = L.lib.dcmesh_step(d, 1, 1, fake, 0, 1, 0.02, 1, None, None, 0, 0, None)
+    assert rc == L.DCMESH_ERR_WORKSPACE
+    rc = L.lib.dcmesh_step(d, 1, 1, fake, 0, 1, 0.02, 1, None, ctypes.c_void_p(0x10000 + 8), 1 << 40, 0, None)
+    assert rc == L.DCMESH_ERR_WORKSPACE                    # misaligned
+    rc = L.lib.dcmesh_step(d, 1, 1, fake, 0, 1, 0.02, 1, None, ctypes.c_void_p(0x10000), 16, 0, None)
+    assert rc == L.DCMESH_ERR_WORKSPACE                    # too small
+    assert b"too small" in L.lib.dcmesh_last_error()
+    rc = L.lib.dcmesh_step(d, 1, 1, None, 0, 1, 0.02, 1, None, ctypes.c_void_p(0x10000), 1 << 40, 0, None)
+    assert rc == L.DCMESH_ERR_INVALID_ARGUMENT             # no A samples
+    rc = L.lib.dcmesh_step(d, 1, 1, fake, 0, 0, 0.02, 1, None, ctypes.c_void_p(0x10000), 1 << 40, 0, None)
+    assert rc == L.DCMESH_ERR_INVALID_ARGUMENT             # a_stride < n_steps
+    rc = L.lib.dcmesh_step(d, 1, 1, fake, 0, 1, float("inf"), 1, None, ctypes.c_void_p(0x10000), 1 << 40, 0, None)
+    assert rc == L.DCMESH_ERR_INVALID_ARGUMENT
+
+
+def test_adjoint_and_density_argument_checks():
+    L = _lib()
+    d = _dom(L)
+    fake = ctypes.c_void_p(0x10000)
+    assert L.lib.dcmesh_adjoint_step(d, 1, 1, None, fake, 0, 0.02, fake, fake, 1 << 40, 0, None) == 1
+    lam = (ctypes.c_void_p * 1)(None)
+    assert L.lib.dcmesh_adjoint_step(d, 1, 1, lam, fake, 0, 0.02, fake, fake, 1 << 40, 0, None) == 1
+    assert L.lib.dcmesh_density(d, 1, 1, fake, 0, None, fake, 1 << 40, 0, None) == 1
+    g = ctypes.c_void_p(None)
+    assert L.lib.dcmesh_graph_create(d, 1, 1, fake, 0, 1, 0.02, 1, None, fake, 1 << 40, 1, None,
+                                     ctypes.byref(g)) == 1       # CHECK_FINITE cannot be captured
+    assert L.lib.dcmesh_graph_launch(None, None) == 1
+    assert L.lib.dcmesh_graph_destroy(None) == 1
+
+
+def test_tuning_options():
+    L = _lib()
+    n = ctypes.c_int32(0)
+    for k in (0, 1, 2):
+        assert L.lib.dcmesh_tuning_options(k, ctypes.byref(n)) == 0 and n.value >= 2
+        assert L.lib.dcmesh_set_tuning(k, n.value) == 1
+        assert L.lib.dcmesh_set_tuning(k, -1) == 0
+    assert L.lib.dcmesh_tuning_options(9, ctypes.byref(n)) == 1
+
+
+def test_workspace_grows_with_problem():
+    L = _lib()
+    out1, out2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.lib.dcmesh_workspace_bytes(_dom(L), 1, 1, 0, ctypes.byref(out1)) == 0
+    assert L.lib.dcmesh_workspace_bytes(_dom(L, n_orb=8), 1, 1, 0, ctypes.byref(out2)) == 0
+    assert out2.value > out1.value
+    assert L.lib.dcmesh_workspace_bytes(_dom(L), 1, 0, 0, ctypes.byref(out2)) == 0   # FP64 is bigger
+    assert out2.value > out1.value
