@@ -196,8 +196,9 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     // z segments: aim at >= 1024 stencil blocks in total, segments of >= 16 planes
     const long long want = std::max<long long>(1, cdiv(1024, std::max<long long>(1, stencil_blocks_xy)));
     D.zseg = (int)std::min<long long>(d.nz, std::max<long long>(16, cdiv(d.nz, want)));
-    D.split_len = n_dom == 1 ? (int)std::min<long long>(2048, std::max<long long>(256, cdiv(cdiv(D.n_grid, 64), kProjKG) * kProjKG))
-                             : 2048;
+    // split-K length depends on the domain alone, so a domain gives the same
+    // bits whether it runs alone or inside a batch
+    D.split_len = (int)std::min<long long>(2048, std::max<long long>(512, cdiv(cdiv(D.n_grid, 32), kProjKG) * kProjKG));
     D.n_split = (int)cdiv(D.n_grid, D.split_len);
     D.a_stride = 3;
   }
@@ -311,7 +312,9 @@ struct Staging {
 std::mutex g_stage_mu;
 std::map<std::pair<size_t, size_t>, std::shared_ptr<Staging>> g_stage;   // (hash, bytes) -> buffer
 
-int stage_tables(const Plan& P, char* work, hipStream_t s, bool capturing, std::shared_ptr<Staging>* keep) {
+// Finds or creates the pinned copy of the tables.  Allocation is not allowed
+// under stream capture, so graph creation calls this before capturing.
+int get_staging(const Plan& P, bool capturing, std::shared_ptr<Staging>* out) {
   const size_t bytes = P.bytes_tables;
   std::vector<char> img(bytes, 0);
   std::memcpy(img.data(), P.desc.data(), sizeof(DomDesc) * P.n_dom);
@@ -333,16 +336,27 @@ int stage_tables(const Plan& P, char* work, hipStream_t s, bool capturing, std::
             ++e;
         }
       }
+      if (capturing)
+        return fail(DCMESH_ERR_UNSUPPORTED,
+                    "these tables were not staged before capture: use dcmesh_graph_create to record steps");
       st = std::make_shared<Staging>();
       HIPCHK(hipHostMalloc(&st->host, bytes, hipHostMallocDefault));
       st->bytes = bytes;
       std::memcpy(st->host, img.data(), bytes);
-      if (!capturing) HIPCHK(hipEventCreateWithFlags(&st->done, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&st->done, hipEventDisableTiming));
       g_stage[{hsh, bytes}] = st;
     }
     if (capturing) st->pinned_forever = true;
   }
-  HIPCHK(hipMemcpyAsync(work, st->host, bytes, hipMemcpyHostToDevice, s));
+  *out = st;
+  return DCMESH_OK;
+}
+
+int stage_tables(const Plan& P, char* work, hipStream_t s, bool capturing, std::shared_ptr<Staging>* keep) {
+  std::shared_ptr<Staging> st;
+  int rc = get_staging(P, capturing, &st);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(work, st->host, P.bytes_tables, hipMemcpyHostToDevice, s));
   if (!capturing && st->done) HIPCHK(hipEventRecord(st->done, s));
   if (keep) *keep = st;
   return DCMESH_OK;
@@ -816,6 +830,16 @@ int dcmesh_graph_create(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<GraphHandle> g(new GraphHandle());
+  {
+    // stage the tables (pinned allocation) before capturing: a dry pass with
+    // zero steps builds the same plan and queues only the table copy
+    CallSetup pre;
+    rc = step_impl(doms, n_dom, precision, a_dev, a_per_domain, a_stride, dt, 0, obs, work, work_bytes, flags,
+                   s, pre);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    pre.keep->pinned_forever = true;
+  }
   CallSetup cs;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   rc = step_impl(doms, n_dom, precision, a_dev, a_per_domain, a_stride, dt, n_steps, obs, work, work_bytes, flags,

@@ -14,9 +14,10 @@
 //       Q'[(p,0)][(n,1)] = Im Q, Q'[(p,1)][(n,1)] = Re Q.
 // A complex product therefore costs 8 M N K real flops, all on MFMA.
 //
-// MFMA shape: 16x16x4 (FP32 and FP64 share the lane layout): operand lane l
-// holds row/column l % 16 and reduction index l / 16; the accumulator lane l
-// holds column l % 16, rows 4 (l / 16) + i, i = 0..3.
+// MFMA shape: 16x16x4.  Operand lane l holds row/column l % 16 and reduction
+// index l / 16 for both FP32 and FP64.  The accumulator lane l holds column
+// l % 16 and four rows: 4 (l / 16) + i for FP32, (l / 16) + 4 i for FP64
+// (i = 0..3), as measured on gfx950.
 #pragma once
 
 #include "common.hpp"
@@ -32,12 +33,14 @@ template <> struct Mfma<float> {
   __device__ __forceinline__ static acc_t run(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ __forceinline__ static int row(int lk, int i) { return 4 * lk + i; }
 };
 template <> struct Mfma<double> {
   using acc_t = f64x4;
   __device__ __forceinline__ static acc_t run(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ __forceinline__ static int row(int lk, int i) { return lk + 4 * i; }
 };
 
 struct ProjArgs {
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ 
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int p = p0 + wm0 + i * 16 + 4 * lk + r;
+        const int p = p0 + wm0 + i * 16 + Mfma<TC>::row(lk, r);
         const int jj = j0 + wn0 + j * 16 + ll;
         if (p < np && jj < no2) part[(long long)p * no2 + jj] = acc[i][j][r];
       }
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ 
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const long long g = g0 + wm0 + i * 16 + Mfma<TC>::row(lk, r);
         const int jj = j0 + wn0 + j * 16 + ll;
         if (g < D.n_grid && jj < no2) {
           TIn* o = out + g * no2 + jj;
