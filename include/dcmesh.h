@@ -84,7 +84,8 @@ enum dcmesh_family {
   DCMESH_FAM_ENERGY = 5,    /* energy finalisation */
   DCMESH_FAM_ADJOINT = 6,   /* gradient inner products and lambda accumulation */
   DCMESH_FAM_OVERLAP = 7,   /* S = h^3 Psi^H Psi */
-  DCMESH_N_FAMILIES = 8
+  DCMESH_FAM_SPLIT = 8,     /* hi/lo operand preparation of the split modes */
+  DCMESH_N_FAMILIES = 9
 };
 
 /* One periodic domain.  nx, ny, nz >= fd_order + 1; fd_order in {2, 4, 6};

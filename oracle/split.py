@@ -79,3 +79,26 @@ def split_complex_matmul(a, b, mode, conj_a=False, sa=0, sb=0):
     else:            # (ar + i ai)(br + i bi)
         out = (rr - ii) + 1j * (ri + ir)
     return out * 2.0 ** (-(sa + sb))
+
+
+def _max_part(z):
+    z = np.asarray(z, dtype=np.complex64)
+    return float(max(np.abs(z.real).max(initial=0.0), np.abs(z.imag).max(initial=0.0)))
+
+
+def apply_vnl_split(dom, u, mode, coef=1.0, occ_scale=False):
+    """coef * B (D o P) with both projector products in two-term split form:
+    P = h^3 split(B^H u), Q = coef D P (f_n) rounded to complex64, then split(B Q).
+    For 'fp16' each operand gets the power-of-two scale of its own largest
+    magnitude (real and imaginary parts together)."""
+    b = np.asarray(dom.proj, dtype=np.complex64)
+    u32 = np.asarray(u, dtype=np.complex64)
+    sb = fp16_scale_exponent(_max_part(b)) if mode == "fp16" else 0
+    su = fp16_scale_exponent(_max_part(u32)) if mode == "fp16" else 0
+    p = dom.h ** 3 * split_complex_matmul(b, u32, mode, conj_a=True, sa=sb, sb=su)
+    q = coef * dom.d[:, None] * p
+    if occ_scale:
+        q = q * dom.occ[None, :]
+    q32 = q.astype(np.complex64)
+    sq = fp16_scale_exponent(_max_part(q32)) if mode == "fp16" else 0
+    return split_complex_matmul(b, q32, mode, sa=sb, sb=sq)

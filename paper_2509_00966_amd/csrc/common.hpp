@@ -57,6 +57,11 @@ struct DomDesc {
   double* energy;               // [.]
   double* grad;                 // [3] gradient accumulator (adjoint)
   double* overlap;              // [n_orb][n_orb] complex128
+  // split-precision operands (16-bit hi and lo planes), null otherwise
+  void* bs_hi; void* bs_lo;     // [N_g][2 n_proj]   projectors as stored
+  void* bt_hi; void* bt_lo;     // [n_proj][2 N_g]   projectors transposed
+  void* qt_hi; void* qt_lo;     // [2 n_orb][2 n_proj] transposed real form of coef D P
+  unsigned* maxbits;            // [4]: max |B|, max |u|, max |Q'| as float bits (FP16 scaling)
 };
 
 // A unit of work: which domain, and up to three tile coordinates.

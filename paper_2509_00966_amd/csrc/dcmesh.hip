@@ -22,6 +22,7 @@
 
 #include "common.hpp"
 #include "gemm.hpp"
+#include "gemm_split.hpp"
 #include "reduce.hpp"
 #include "stencil.hpp"
 
@@ -47,6 +48,7 @@ size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 
 bool is_fp64(int prec) { return prec == DCMESH_FP64; }
+bool is_split(int prec) { return prec == DCMESH_SPLIT_BF16 || prec == DCMESH_SPLIT_FP16; }
 size_t real_size(int prec) { return is_fp64(prec) ? 8 : 4; }
 
 // ---------------------------------------------------------------------------
@@ -111,8 +113,6 @@ int validate_domains(const dcmesh_domain* doms, int32_t n_dom, int32_t prec) {
     if (!d.psi || !d.v_loc || !d.occ) return fail(DCMESH_ERR_INVALID_ARGUMENT, "psi, v_loc and occ are required" + at);
     if (d.n_proj > 0 && (!d.proj || !d.d)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "proj and d are required when n_proj > 0" + at);
   }
-  if (prec == DCMESH_SPLIT_BF16 || prec == DCMESH_SPLIT_FP16)
-    return fail(DCMESH_ERR_UNSUPPORTED, "split-precision modes are not available in this build");
   return DCMESH_OK;
 }
 
@@ -138,6 +138,7 @@ struct Plan {
   std::vector<DomDesc> desc;
   std::vector<Item> items;
   std::vector<Launch> stencil, proj, reduce, corr, dens, elem, energy, ovl_proj, ovl_reduce;
+  std::vector<Launch> presplit, absmax_b, absmax_u, splitq;   // split-precision modes
   size_t bytes_tables = 0, bytes_total = 0;
   size_t off_items = 0, off_flag = 0;
   bool any_proj = false;
@@ -267,6 +268,27 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     for (long long b = 0; b < cdiv((long long)D.n_orb * D.n_orb, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
   });
 
+  if (is_split(prec)) {
+    auto has_p = [&](int i) { return doms[i].n_proj > 0 ? 0 : -1; };
+    group_launch(P.presplit, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
+      const DomDesc& D = P.desc[i];
+      for (long long gt = 0; gt < cdiv(D.n_grid, 32); ++gt)
+        for (int pt = 0; pt < cdiv(D.n_proj, 32); ++pt) it.push_back({i, (int)gt, pt, 0});
+    });
+    group_launch(P.absmax_b, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
+      const DomDesc& D = P.desc[i];
+      for (long long b = 0; b < cdiv(D.n_grid * 2 * D.n_proj, (long long)kBlock * 16); ++b) it.push_back({i, (int)b, 0, 0});
+    });
+    group_launch(P.absmax_u, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
+      const DomDesc& D = P.desc[i];
+      for (long long b = 0; b < cdiv(D.n_grid * 2 * D.n_orb, (long long)kBlock * 16); ++b) it.push_back({i, (int)b, 0, 0});
+    });
+    group_launch(P.splitq, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
+      const DomDesc& D = P.desc[i];
+      for (long long b = 0; b < cdiv(4LL * D.n_proj * D.n_orb, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
+    });
+  }
+
   // workspace layout
   size_t off = 0;
   off += align_up(sizeof(DomDesc) * n_dom);
@@ -292,6 +314,14 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.e_loc = (double*)take(sizeof(double) * std::max(1, D.n_e_loc));
     D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
     D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
+    if (is_split(prec) && D.n_proj > 0) {
+      const size_t nb = (size_t)D.n_grid * 2 * D.n_proj * 2;   // 16-bit values
+      D.bs_hi = take(nb); D.bs_lo = take(nb);
+      D.bt_hi = take(nb); D.bt_lo = take(nb);
+      const size_t nq = (size_t)4 * D.n_orb * D.n_proj * 2;
+      D.qt_hi = take(nq); D.qt_lo = take(nq);
+      D.maxbits = (unsigned*)take(4 * sizeof(unsigned));
+    }
   }
   P.bytes_total = off;
 }
@@ -497,7 +527,7 @@ void launch_project(const Ctx& c, int u_slot) {
 template <typename T>
 void launch_reduce(const Ctx& c, double cre, double cim, int occ_scale, int want_energy) {
   ProfScope prof_(DCMESH_FAM_REDUCE, c.s);
-  ReduceArgs a{cre, cim, occ_scale, want_energy, 0};
+  ReduceArgs a{cre, cim, occ_scale, want_energy, 0, c.P->prec == DCMESH_SPLIT_FP16 ? 1 : 0};
   for (const Launch& L : c.P->reduce)
     k_reduce<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
 }
@@ -526,18 +556,96 @@ void launch_correct(const Ctx& c, int out_slot) {
   }
 }
 
+// ---- split-precision launches ----
+void launch_zero_maxbits(const Ctx& c, int which) {
+  for (const Launch& L : c.P->energy)
+    k_zero_maxbits<<<cdiv(L.count, kBlock), kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, L.count, which);
+}
+
+// Once per call: the 16-bit hi/lo planes of the projectors (and, for FP16,
+// the max |B| that fixes their scale).
+void launch_presplit(const Ctx& c) {
+  ProfScope prof_(DCMESH_FAM_SPLIT, c.s);
+  const bool f16 = c.P->prec == DCMESH_SPLIT_FP16;
+  if (f16) {
+    launch_zero_maxbits(c, 0);
+    for (const Launch& L : c.P->absmax_b) k_absmax<<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, 0, 0);
+  }
+  for (const Launch& L : c.P->presplit) {
+    if (f16)
+      k_presplit<1><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+    else
+      k_presplit<0><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+  }
+}
+
+template <int MODE>
+void launch_project_split(const Ctx& c, int u_slot) {
+  if (MODE == 1) {
+    ProfScope prof_(DCMESH_FAM_SPLIT, c.s);
+    launch_zero_maxbits(c, 1);
+    for (const Launch& L : c.P->absmax_u)
+      k_absmax<<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, 1, u_slot);
+  }
+  ProfScope prof_(DCMESH_FAM_PROJECT, c.s);
+  for (const Launch& L : c.P->proj) {
+    const Item* it = c.d_items + L.first;
+    const dim3 g(L.count), b(kBlock);
+    switch (L.variant) {
+      case 0: k_project_split<MODE, 128, 128, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      case 1: k_project_split<MODE, 64, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      case 2: k_project_split<MODE, 64, 128, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      default: k_project_split<MODE, 128, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+    }
+  }
+}
+
+template <int MODE>
+void launch_correct_split(const Ctx& c, int out_slot) {
+  {
+    ProfScope prof_(DCMESH_FAM_SPLIT, c.s);
+    for (const Launch& L : c.P->splitq) k_split_q<MODE><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+  }
+  ProfScope prof_(DCMESH_FAM_CORRECT, c.s);
+  for (const Launch& L : c.P->corr) {
+    const Item* it = c.d_items + L.first;
+    const dim3 g(L.count), b(kBlock);
+    switch (L.variant) {
+      case 0: k_correct_split<MODE, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      case 1: k_correct_split<MODE, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      case 2: k_correct_split<MODE, 64, 64, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      default: k_correct_split<MODE, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+    }
+  }
+}
+
 // out = base + coef * f^occ * H(A_step) u   (full H: local sweep, then the
 // projector correction added in place).
 template <typename T>
 void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double cre, double cim,
                  int occ_scale, int step, int want_energy) {
+  const int prec = c.P->prec;
   if (c.P->any_proj) {
-    launch_project<T>(c, u_slot);
+    if (prec == DCMESH_SPLIT_BF16) {
+      launch_project_split<0>(c, u_slot);
+    } else if (prec == DCMESH_SPLIT_FP16) {
+      launch_project_split<1>(c, u_slot);
+      launch_zero_maxbits(c, 2);
+    } else {
+      launch_project<T>(c, u_slot);
+    }
     launch_reduce<T>(c, cre, cim, occ_scale, want_energy);
   }
   StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy};
   launch_stencil<T>(c, sa);
-  if (c.P->any_proj) launch_correct<T>(c, out_slot);
+  if (c.P->any_proj) {
+    if (prec == DCMESH_SPLIT_BF16)
+      launch_correct_split<0>(c, out_slot);
+    else if (prec == DCMESH_SPLIT_FP16)
+      launch_correct_split<1>(c, out_slot);
+    else
+      launch_correct<T>(c, out_slot);
+  }
 }
 
 template <typename T>
@@ -571,7 +679,7 @@ void launch_overlap(const Ctx& c) {
   ProjArgs a{SLOT_PSI, SLOT_PSI, 1};
   for (const Launch& L : c.P->ovl_proj)
     k_project<T, double, 64, 64, kProjKG><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
-  ReduceArgs r{1.0, 0.0, 0, 0, 1};
+  ReduceArgs r{1.0, 0.0, 0, 0, 1, 0};
   for (const Launch& L : c.P->ovl_reduce) k_reduce<double><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, r);
 }
 
@@ -607,6 +715,7 @@ int prepare(CallSetup& cs, const dcmesh_domain* doms, int32_t n_dom, int32_t pre
 template <typename T>
 int run_step(CallSetup& cs, int32_t n_steps, double dt, bool want_rho_j, bool want_e) {
   const Ctx& c = cs.c;
+  if (is_split(c.P->prec) && c.P->any_proj && n_steps > 0) launch_presplit(c);
   for (int k = 0; k < n_steps; ++k) {
     if (want_rho_j) launch_density<T>(c, k, k);
     apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0);
@@ -748,6 +857,7 @@ int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, 
   });
   if (rc) return rc;
   const bool f64 = is_fp64(precision);
+  if (is_split(precision) && cs.P.any_proj && (e || hpsi)) launch_presplit(cs.c);
   if (rho_j) f64 ? launch_density<double>(cs.c, 0, 0) : launch_density<float>(cs.c, 0, 0);
   if (e || hpsi) {
     if (f64) {
@@ -791,6 +901,7 @@ int dcmesh_adjoint_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
   auto body = [&](auto tag) {
     using T = decltype(tag);
     const Ctx& c = cs.c;
+    if (is_split(precision) && c.P->any_proj) launch_presplit(c);
     // forward Horner intermediates: u3 -> B0, u2 -> B1, u1 -> B2 (u4 = psi)
     apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, 0, 0);
     apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, 0, 0);

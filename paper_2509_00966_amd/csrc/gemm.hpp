@@ -129,6 +129,7 @@ struct ReduceArgs {
   int occ_scale;       // fold f_n into Q
   int want_energy;     // nonlocal energy partials sum f D |P|^2
   int write_overlap;   // overlap mode: write h^3 * sum to D.overlap (complex128)
+  int want_qmax;       // gather max |Q'| into D.maxbits[2] (FP16 split scaling)
 };
 
 // Items: (dom, block index over n_proj * n_orb pairs).  Deterministic: the
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
   const long long idx = (long long)it.a * kBlock + threadIdx.x;
   const bool ok = idx < (long long)np * no;
   double e = 0.0;
+  float qmax = 0.f;
   if (ok) {
     const int p = (int)(idx / no), n = (int)(idx % no);
     const TC* part = (const TC*)D.ppart;
@@ -173,7 +175,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
       Q[(long long)(2 * p + 1) * no2 + 2 * n] = -qi;
       Q[(long long)(2 * p + 1) * no2 + 2 * n + 1] = qr;
       if (args.want_energy) e = (double)fn * (double)dp * ((double)pr * pr + (double)pi * pi);
+      qmax = fmaxf(fabsf((float)qr), fabsf((float)qi));
     }
+  }
+  if (args.want_qmax) {
+    float m = qmax;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&D.maxbits[2], __float_as_uint(m));
   }
   if (args.want_energy) {
     const double s = block_sum(e, red);

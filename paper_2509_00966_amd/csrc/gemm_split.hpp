@@ -1,0 +1,363 @@
+// Split-precision projector products (the hi+lo BF16 / FP16 modes of
+// Sec. VI.C, here with two terms per operand): every FP32 operand value x is
+// written as hi + lo with hi = round16(x) and lo = round16(x - hi), and each
+// real product is accumulated in FP32 as hi*hi + hi*lo + lo*hi on the 16-bit
+// matrix cores (v_mfma_f32_16x16x32_{bf16,f16}).  FP16 operands are first
+// scaled by a power of two 2^s chosen from the operand's largest magnitude
+// (max |x| 2^s in [2^14, 2^15)) so both terms stay in FP16 range; the sums are
+// scaled back by 2^-(s_a + s_b).
+//
+// Operand storage (all 16-bit, hi and lo in separate planes):
+//   Bs[g][k]   k = 2p + c : the projectors as stored (correction, A operand)
+//   Bt[p][k]   k = 2g + c : transposed (projection, A operand)
+//   Qt[j][k]   k = 2p + c : transposed real form of coef D P (correction, B operand)
+// and the projection's right operand u is split while it is staged into LDS.
+// MFMA 16x16x32 lane layout: operand lane l holds row/column l % 16 and the 8
+// consecutive reduction indices 8 (l / 16) .. 8 (l / 16) + 7; accumulator lane
+// l holds column l % 16, rows 4 (l / 16) + i.
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace dcm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int MODE> struct Half;
+template <> struct Half<0> {   // BF16
+  using T = __bf16;
+  using V8 = bf16x8;
+  __device__ __forceinline__ static f32x4 mma(V8 a, V8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Half<1> {   // FP16
+  using T = _Float16;
+  using V8 = f16x8;
+  __device__ __forceinline__ static f32x4 mma(V8 a, V8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// hi/lo of x * 2^s (s = 0 for BF16)
+template <int MODE>
+__device__ __forceinline__ void split2(float x, float scale, typename Half<MODE>::T& hi, typename Half<MODE>::T& lo) {
+  using T = typename Half<MODE>::T;
+  const float xs = x * scale;
+  hi = (T)xs;
+  lo = (T)(xs - (float)hi);
+}
+
+// Power-of-two scale from the bits of a max |x| (FP16 mode): s = 15 - e with
+// max = m 2^e, m in [0.5, 1).  Returns 2^s; 1 when max is 0.
+__device__ __forceinline__ float fp16_scale_from_bits(unsigned bits) {
+  const float m = __uint_as_float(bits);
+  if (m == 0.0f) return 1.0f;
+  int e;
+  (void)frexpf(m, &e);
+  return ldexpf(1.0f, 15 - e);
+}
+
+// max |x| over a real array of n values into *bits (atomic max on the float
+// bits, exact and order independent).  Items: (dom, block); which: 0 = B, 1 = slot u.
+__global__ __launch_bounds__(kBlock) void k_absmax(const DomDesc* __restrict__ doms, const Item* __restrict__ items,
+                                                   int which, int u_slot) {
+  __shared__ float red[4];
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const float* x = which == 0 ? (const float*)D.proj : (const float*)D.slot[u_slot];
+  const long long n = which == 0 ? D.n_grid * 2 * D.n_proj : D.n_grid * 2 * D.n_orb;
+  float m = 0.f;
+  const long long base = (long long)it.a * kBlock * 16;
+  for (int i = 0; i < 16; ++i) {
+    const long long e = base + (long long)i * kBlock + threadIdx.x;
+    if (e < n) m = fmaxf(m, fabsf(x[e]));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float b = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    atomicMax(&D.maxbits[which == 0 ? 0 : 1], __float_as_uint(b));
+  }
+}
+
+// Clears maxbits[which] of every domain.  Items: one per domain.
+__global__ void k_zero_maxbits(const DomDesc* __restrict__ doms, const Item* __restrict__ items, int n_items,
+                               int which) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_items) {
+    unsigned* m = doms[items[i].dom].maxbits;
+    if (m) m[which] = 0u;
+  }
+}
+
+// Pre-split of the projectors: Bs (natural layout) and Bt (transposed), hi and
+// lo.  Items: (dom, 32-row g tile, 32-column p tile).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_presplit(const DomDesc* __restrict__ doms, const Item* __restrict__ items) {
+  using T = typename Half<MODE>::T;
+  __shared__ float tile[32][65];     // 32 g x (32 p x re/im)
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, k2 = 2 * np;
+  const long long g0 = (long long)it.a * 32;
+  const int p0 = it.b * 32;
+  const float scale = MODE == 1 ? fp16_scale_from_bits(D.maxbits[0]) : 1.0f;
+  const float* B = (const float*)D.proj;
+  for (int idx = threadIdx.x; idx < 32 * 64; idx += kBlock) {
+    const int r = idx / 64, c = idx % 64;
+    const long long g = g0 + r;
+    const int k = 2 * p0 + c;
+    float v = 0.f;
+    if (g < D.n_grid && k < k2) {
+      v = B[g * k2 + k];
+      T hi, lo;
+      split2<MODE>(v, scale, hi, lo);
+      ((T*)D.bs_hi)[g * k2 + k] = hi;
+      ((T*)D.bs_lo)[g * k2 + k] = lo;
+    }
+    tile[r][c] = v;
+  }
+  __syncthreads();
+  // transposed: Bt[p][2g + c]
+  for (int idx = threadIdx.x; idx < 32 * 64; idx += kBlock) {
+    const int pr = idx / 64, q = idx % 64;      // q = 2 * g_local + c
+    const int gl = q / 2, c = q % 2;
+    const int p = p0 + pr;
+    const long long g = g0 + gl;
+    if (p < np && g < D.n_grid) {
+      T hi, lo;
+      split2<MODE>(tile[gl][2 * pr + c], scale, hi, lo);
+      const long long o = (long long)p * (2 * D.n_grid) + 2 * g + c;
+      ((T*)D.bt_hi)[o] = hi;
+      ((T*)D.bt_lo)[o] = lo;
+    }
+  }
+}
+
+// Projection partials: part[s][p][j] = sum over the split's grid points of the
+// real-form product, from Bt (16-bit, pre-split) and u (FP32, split here).
+// Items: (dom, p tile, j tile, split).  KG grid points (2 KG reduction indices)
+// per LDS stage; 2 KG must be a multiple of 32.
+template <int MODE, int BM, int BN, int KG>
+__global__ __launch_bounds__(kBlock) void k_project_split(const DomDesc* __restrict__ doms,
+                                                          const Item* __restrict__ items,
+                                                          int u_slot) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int KK = 2 * KG;                 // reduction indices per stage
+  constexpr int LK = KK + 8;                 // padded row (halves)
+  constexpr int TM = BM / 32, TN = BN / 32;
+  static_assert(KK % 32 == 0, "stage must hold whole MFMA steps");
+  __shared__ __align__(16) T sAh[BM * LK];
+  __shared__ __align__(16) T sAl[BM * LK];
+  __shared__ __align__(16) T sBh[BN * LK];
+  __shared__ __align__(16) T sBl[BN * LK];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no2 = 2 * D.n_orb;
+  const long long ng2 = 2 * D.n_grid;
+  const int p0 = it.a * BM, j0 = it.b * BN;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+  const float* __restrict__ U = (const float*)D.slot[u_slot];
+  const T* __restrict__ bth = (const T*)D.bt_hi;
+  const T* __restrict__ btl = (const T*)D.bt_lo;
+  const float su = MODE == 1 ? fp16_scale_from_bits(D.maxbits[1]) : 1.0f;
+  const float sbs = MODE == 1 ? fp16_scale_from_bits(D.maxbits[0]) : 1.0f;
+
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BN / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  for (long long gc = g_begin; gc < g_end; gc += KG) {
+    // A: rows p, reduction indices [2 gc, 2 gc + KK) of Bt
+    for (int idx = threadIdx.x; idx < BM * KK; idx += kBlock) {
+      const int r = idx / KK, q = idx % KK;
+      const int p = p0 + r;
+      const long long k = 2 * gc + q;
+      const bool ok = p < np && k < 2 * g_end;
+      sAh[r * LK + q] = ok ? bth[(long long)p * ng2 + k] : (T)0.f;
+      sAl[r * LK + q] = ok ? btl[(long long)p * ng2 + k] : (T)0.f;
+    }
+    // B: columns j, k = 2 g_local + c: c = 0 -> u[g][j], c = 1 -> (j even: u[g][j+1], j odd: -u[g][j-1])
+    for (int idx = threadIdx.x; idx < KG * (BN / 2); idx += kBlock) {
+      const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+      const long long g = gc + gl;
+      const int j = j0 + 2 * nn;
+      float re = 0.f, im = 0.f;
+      if (g < g_end && j < no2) {
+        re = U[g * no2 + j];
+        im = U[g * no2 + j + 1];
+      }
+      T rh, rl, ih, il;
+      split2<MODE>(re, su, rh, rl);
+      split2<MODE>(im, su, ih, il);
+      const int c0 = (2 * nn) * LK + 2 * gl, c1 = (2 * nn + 1) * LK + 2 * gl;
+      sBh[c0] = rh; sBh[c0 + 1] = ih; sBh[c1] = ih; sBh[c1 + 1] = (T)(-(float)rh);
+      sBl[c0] = rl; sBl[c0 + 1] = il; sBl[c1] = il; sBl[c1 + 1] = (T)(-(float)rl);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KK / 32; ++ks) {
+      V8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int o = (wm0 + i * 16 + ll) * LK + ks * 32 + 8 * lk;
+        ah[i] = *(const V8*)&sAh[o];
+        al[i] = *(const V8*)&sAl[o];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int o = (wn0 + j * 16 + ll) * LK + ks * 32 + 8 * lk;
+        bh[j] = *(const V8*)&sBh[o];
+        bl[j] = *(const V8*)&sBl[o];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = Half<MODE>::mma(ah[i], bh[j], acc[i][j]);
+          acc[i][j] = Half<MODE>::mma(ah[i], bl[j], acc[i][j]);
+          acc[i][j] = Half<MODE>::mma(al[i], bh[j], acc[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  const float unscale = 1.0f / (su * sbs);
+  float* __restrict__ part = (float*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (p < np && jj < no2) part[(long long)p * no2 + jj] = acc[i][j][r] * unscale;
+      }
+}
+
+// Q'^T hi/lo from the FP32 real form Q' (written by k_reduce).  FP16 mode uses
+// the max of |Q'| gathered with an atomic by the same k_reduce launch.
+// Items: (dom, block over 2 n_orb x 2 n_proj entries).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_split_q(const DomDesc* __restrict__ doms, const Item* __restrict__ items) {
+  using T = typename Half<MODE>::T;
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int k2 = 2 * D.n_proj, no2 = 2 * D.n_orb;
+  const long long idx = (long long)it.a * kBlock + threadIdx.x;
+  if (idx >= (long long)k2 * no2) return;
+  const int j = (int)(idx / k2), k = (int)(idx % k2);
+  const float scale = MODE == 1 ? fp16_scale_from_bits(D.maxbits[2]) : 1.0f;
+  T hi, lo;
+  split2<MODE>(((const float*)D.qmat)[(long long)k * no2 + j], scale, hi, lo);
+  ((T*)D.qt_hi)[idx] = hi;
+  ((T*)D.qt_lo)[idx] = lo;
+}
+
+// out[g][j] += sum_k Bs[g][k] Qt[j][k] (hi*hi + hi*lo + lo*hi), unscaled.
+// Items: (dom, g tile, j tile).  KC reduction indices per LDS stage.
+template <int MODE, int BMG, int BN, int KC>
+__global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restrict__ doms,
+                                                          const Item* __restrict__ items,
+                                                          int out_slot) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int LK = KC + 8;
+  constexpr int TM = BMG / 32, TN = BN / 32;
+  static_assert(KC % 32 == 0, "stage must hold whole MFMA steps");
+  __shared__ __align__(16) T sAh[BMG * LK];
+  __shared__ __align__(16) T sAl[BMG * LK];
+  __shared__ __align__(16) T sBh[BN * LK];
+  __shared__ __align__(16) T sBl[BN * LK];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int K = 2 * D.n_proj, no2 = 2 * D.n_orb;
+  const long long g0 = (long long)it.a * BMG;
+  const int j0 = it.b * BN;
+  const T* __restrict__ ah_g = (const T*)D.bs_hi;
+  const T* __restrict__ al_g = (const T*)D.bs_lo;
+  const T* __restrict__ bh_g = (const T*)D.qt_hi;
+  const T* __restrict__ bl_g = (const T*)D.qt_lo;
+  float* __restrict__ out = (float*)D.slot[out_slot];
+
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wm0 = (wv / 2) * (BMG / 2), wn0 = (wv % 2) * (BN / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int idx = threadIdx.x; idx < BMG * KC; idx += kBlock) {
+      const int r = idx / KC, q = idx % KC;
+      const long long g = g0 + r;
+      const int k = k0 + q;
+      const bool ok = g < D.n_grid && k < K;
+      sAh[r * LK + q] = ok ? ah_g[g * K + k] : (T)0.f;
+      sAl[r * LK + q] = ok ? al_g[g * K + k] : (T)0.f;
+    }
+    for (int idx = threadIdx.x; idx < BN * KC; idx += kBlock) {
+      const int r = idx / KC, q = idx % KC;
+      const int j = j0 + r, k = k0 + q;
+      const bool ok = j < no2 && k < K;
+      sBh[r * LK + q] = ok ? bh_g[(long long)j * K + k] : (T)0.f;
+      sBl[r * LK + q] = ok ? bl_g[(long long)j * K + k] : (T)0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC / 32; ++ks) {
+      V8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int o = (wm0 + i * 16 + ll) * LK + ks * 32 + 8 * lk;
+        ah[i] = *(const V8*)&sAh[o];
+        al[i] = *(const V8*)&sAl[o];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int o = (wn0 + j * 16 + ll) * LK + ks * 32 + 8 * lk;
+        bh[j] = *(const V8*)&sBh[o];
+        bl[j] = *(const V8*)&sBl[o];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = Half<MODE>::mma(ah[i], bh[j], acc[i][j]);
+          acc[i][j] = Half<MODE>::mma(ah[i], bl[j], acc[i][j]);
+          acc[i][j] = Half<MODE>::mma(al[i], bh[j], acc[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  const float unscale = MODE == 1 ? 1.0f / (fp16_scale_from_bits(D.maxbits[0]) * fp16_scale_from_bits(D.maxbits[2]))
+                                  : 1.0f;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && jj < no2) out[g * no2 + jj] += acc[i][j][r] * unscale;
+      }
+}
+
+}  // namespace dcm
