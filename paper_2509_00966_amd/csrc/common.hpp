@@ -40,7 +40,8 @@ struct DomDesc {
   // workspace (accumulation type of the projector products)
   void* ppart;                  // [n_split][n_proj][2 n_orb] split-K partials
   void* pmat;                   // [n_proj][2 n_orb]  P = h^3 B^H u
-  void* qmat;                   // [2 n_proj][2 n_orb] real form of coef D P
+  void* qmat;                   // [2 n_proj][ldq] real form of coef D P
+  long long ldq;                // row stride of qmat: 2 n_orb rounded up to 4
   double* e_loc;                // [n_stencil_items] local-energy partials
   double* e_nl;                 // [n_reduce_items] nonlocal-energy partials
   double* g_part;               // [n_grad_items][3] gradient partials
@@ -58,10 +59,11 @@ struct DomDesc {
   double* grad;                 // [3] gradient accumulator (adjoint)
   double* overlap;              // [n_orb][n_orb] complex128
   // split-precision operands (16-bit hi and lo planes), null otherwise
-  void* bs_hi; void* bs_lo;     // [N_g][2 n_proj]   projectors as stored
-  void* bt_hi; void* bt_lo;     // [n_proj][2 N_g]   projectors transposed
-  void* qt_hi; void* qt_lo;     // [2 n_orb][2 n_proj] transposed real form of coef D P
+  void* bs_hi; void* bs_lo;     // [N_g][ldbs]       projectors as stored
+  void* bt_hi; void* bt_lo;     // [n_proj][ldbt]    projectors transposed
+  void* qt_hi; void* qt_lo;     // [2 n_orb][ldqt]   transposed real form of coef D P
   unsigned* maxbits;            // [4]: max |B|, max |u|, max |Q'| as float bits (FP16 scaling)
+  long long ldbs, ldbt, ldqt;   // row strides (halves) of bs, bt, qt: multiples of 8, zero padded
 };
 
 // A unit of work: which domain, and up to three tile coordinates.

@@ -74,14 +74,27 @@ int stencil_variant(const dcmesh_domain&, int) {
   const int t = g_tune[DCMESH_KERNEL_STENCIL].load();
   return t >= 0 ? t : 0;
 }
-int proj_variant(const dcmesh_domain& d, int prec) {
+// FP32 projector products load rows with 16-byte vectors when every row
+// length is a multiple of 4 floats, else with 8-byte (one complex) vectors;
+// the launch key carries that choice as variant + 4.
+int wide_proj(const dcmesh_domain& d, int prec) {
+  return (!is_fp64(prec) && !is_split(prec) && d.n_proj % 2 == 0 && d.n_orb % 2 == 0) ? 4 : 0;
+}
+int wide_corr(const dcmesh_domain& d, int prec) {
+  return (!is_fp64(prec) && !is_split(prec) && d.n_proj % 2 == 0) ? 4 : 0;
+}
+int proj_variant_base(const dcmesh_domain& d, int prec);
+int corr_variant_base(const dcmesh_domain& d, int prec);
+int proj_variant(const dcmesh_domain& d, int prec) { return proj_variant_base(d, prec) + wide_proj(d, prec); }
+int corr_variant(const dcmesh_domain& d, int prec) { return corr_variant_base(d, prec) + wide_corr(d, prec); }
+int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
   const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
   return bigm ? (bign ? 0 : 3) : (bign ? 2 : 1);
 }
-int corr_variant(const dcmesh_domain& d, int prec) {
+int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
@@ -202,6 +215,9 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.split_len = (int)std::min<long long>(2048, std::max<long long>(512, cdiv(cdiv(D.n_grid, 32), kProjKG) * kProjKG));
     D.n_split = (int)cdiv(D.n_grid, D.split_len);
     D.a_stride = 3;
+    D.ldq = (2 * D.n_orb + 3) / 4 * 4;
+    D.ldbs = D.ldqt = (2 * (long long)D.n_proj + 7) / 8 * 8;
+    D.ldbt = (2 * D.n_grid + 7) / 8 * 8;
   }
   P.any_proj = false;
   for (int i = 0; i < n_dom; ++i) P.any_proj |= doms[i].n_proj > 0;
@@ -222,7 +238,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
 
   auto pv = [&](int i) { return doms[i].n_proj > 0 ? proj_variant(doms[i], prec) : -1; };
   group_launch(P.proj, P.items, n_dom, pv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i)] : kProjF32[pv(i)];
+    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i) % 4] : kProjF32[pv(i) % 4];
     const DomDesc& D = P.desc[i];
     for (int s = 0; s < D.n_split; ++s)
       for (int mt = 0; mt < cdiv(D.n_proj, t.bm); ++mt)
@@ -238,7 +254,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_e_nl++;
   auto cv = [&](int i) { return doms[i].n_proj > 0 ? corr_variant(doms[i], prec) : -1; };
   group_launch(P.corr, P.items, n_dom, cv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i)] : kCorrF32[cv(i)];
+    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i) % 4] : kCorrF32[cv(i) % 4];
     const DomDesc& D = P.desc[i];
     for (long long gt = 0; gt < cdiv(D.n_grid, t.bm); ++gt)
       for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, (int)gt, nt, 0});
@@ -272,8 +288,10 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     auto has_p = [&](int i) { return doms[i].n_proj > 0 ? 0 : -1; };
     group_launch(P.presplit, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
       const DomDesc& D = P.desc[i];
-      for (long long gt = 0; gt < cdiv(D.n_grid, 32); ++gt)
-        for (int pt = 0; pt < cdiv(D.n_proj, 32); ++pt) it.push_back({i, (int)gt, pt, 0});
+      const long long ngt = std::max(cdiv(D.n_grid, 32), cdiv(D.ldbt, 64));
+      const long long npt = std::max(cdiv(D.n_proj, 32), cdiv(D.ldbs, 64));
+      for (long long gt = 0; gt < ngt; ++gt)
+        for (int pt = 0; pt < npt; ++pt) it.push_back({i, (int)gt, pt, 0});
     });
     group_launch(P.absmax_b, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
       const DomDesc& D = P.desc[i];
@@ -285,7 +303,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     });
     group_launch(P.splitq, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
       const DomDesc& D = P.desc[i];
-      for (long long b = 0; b < cdiv(4LL * D.n_proj * D.n_orb, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
+      for (long long b = 0; b < cdiv(2LL * D.n_orb * D.ldqt, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
     });
   }
 
@@ -310,15 +328,15 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     const size_t part = std::max((size_t)D.n_split * D.n_proj * no2 * acc, (size_t)D.n_split * D.n_orb * no2 * 8);
     D.ppart = take(part);
     D.pmat = take((size_t)D.n_proj * no2 * acc);
-    D.qmat = take(2 * (size_t)D.n_proj * no2 * acc);
+    D.qmat = take(2 * (size_t)D.n_proj * D.ldq * acc);
     D.e_loc = (double*)take(sizeof(double) * std::max(1, D.n_e_loc));
     D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
     D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
     if (is_split(prec) && D.n_proj > 0) {
-      const size_t nb = (size_t)D.n_grid * 2 * D.n_proj * 2;   // 16-bit values
-      D.bs_hi = take(nb); D.bs_lo = take(nb);
-      D.bt_hi = take(nb); D.bt_lo = take(nb);
-      const size_t nq = (size_t)4 * D.n_orb * D.n_proj * 2;
+      const size_t nbs = (size_t)D.n_grid * D.ldbs * 2, nbt = (size_t)D.n_proj * D.ldbt * 2;   // 16-bit values
+      D.bs_hi = take(nbs); D.bs_lo = take(nbs);
+      D.bt_hi = take(nbt); D.bt_lo = take(nbt);
+      const size_t nq = (size_t)2 * D.n_orb * D.ldqt * 2;
       D.qt_hi = take(nq); D.qt_lo = take(nq);
       D.maxbits = (unsigned*)take(4 * sizeof(unsigned));
     }
@@ -508,17 +526,21 @@ void launch_project(const Ctx& c, int u_slot) {
     const dim3 g(L.count), b(kBlock);
     if constexpr (sizeof(T) == 4) {
       switch (L.variant) {
-        case 0: k_project<T, T, 128, 128, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        case 1: k_project<T, T, 64, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        case 2: k_project<T, T, 64, 128, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        default: k_project<T, T, 128, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 0: k_project<T, T, 128, 128, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 1: k_project<T, T, 64, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 2: k_project<T, T, 64, 128, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 3: k_project<T, T, 128, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 4: k_project<T, T, 128, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 5: k_project<T, T, 64, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 6: k_project<T, T, 64, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        default: k_project<T, T, 128, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
       }
     } else {
       switch (L.variant) {
-        case 0: k_project<T, T, 64, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        case 1: k_project<T, T, 32, 32, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        case 2: k_project<T, T, 64, 32, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        default: k_project<T, T, 32, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 0: k_project<T, T, 64, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 1: k_project<T, T, 32, 32, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 2: k_project<T, T, 64, 32, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        default: k_project<T, T, 32, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
       }
     }
   }
@@ -540,17 +562,21 @@ void launch_correct(const Ctx& c, int out_slot) {
     const dim3 g(L.count), b(kBlock);
     if constexpr (sizeof(T) == 4) {
       switch (L.variant) {
-        case 0: k_correct<T, T, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        case 1: k_correct<T, T, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        case 2: k_correct<T, T, 64, 64, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        default: k_correct<T, T, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 0: k_correct<T, T, 64, 256, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 1: k_correct<T, T, 64, 128, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 2: k_correct<T, T, 64, 64, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 3: k_correct<T, T, 128, 128, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 4: k_correct<T, T, 64, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 5: k_correct<T, T, 64, 128, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 6: k_correct<T, T, 64, 64, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        default: k_correct<T, T, 128, 128, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       }
     } else {
       switch (L.variant) {
-        case 0: k_correct<T, T, 64, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        case 1: k_correct<T, T, 32, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        case 2: k_correct<T, T, 64, 32, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        default: k_correct<T, T, 32, 32, 16><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 0: k_correct<T, T, 64, 64, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 1: k_correct<T, T, 32, 64, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 2: k_correct<T, T, 64, 32, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        default: k_correct<T, T, 32, 32, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       }
     }
   }
@@ -678,7 +704,7 @@ void launch_overlap(const Ctx& c) {
   ProfScope prof_(DCMESH_FAM_OVERLAP, c.s);
   ProjArgs a{SLOT_PSI, SLOT_PSI, 1};
   for (const Launch& L : c.P->ovl_proj)
-    k_project<T, double, 64, 64, kProjKG><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
+    k_project<T, double, 64, 64, kProjKG, 2><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
   ReduceArgs r{1.0, 0.0, 0, 0, 1, 0};
   for (const Launch& L : c.P->ovl_reduce) k_reduce<double><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, r);
 }

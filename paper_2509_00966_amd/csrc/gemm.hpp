@@ -14,6 +14,10 @@
 //       Q'[(p,0)][(n,1)] = Im Q, Q'[(p,1)][(n,1)] = Re Q.
 // A complex product therefore costs 8 M N K real flops, all on MFMA.
 //
+// Both kernels stream their tiles with 16-byte (VW = 4 floats / 2 doubles) or
+// 8-byte (VW = 2 floats, odd row lengths) global loads into registers, one
+// chunk ahead of the MFMA work on the chunk held in LDS.
+//
 // MFMA shape: 16x16x4.  Operand lane l holds row/column l % 16 and reduction
 // index l / 16 for both FP32 and FP64.  The accumulator lane l holds column
 // l % 16 and four rows: 4 (l / 16) + i for FP32, (l / 16) + 4 i for FP64
@@ -43,21 +47,39 @@ template <> struct Mfma<double> {
   __device__ __forceinline__ static int row(int lk, int i) { return lk + 4 * i; }
 };
 
+// A short vector of VW elements of T moved as one load / store.
+template <typename T, int VW> struct alignas(sizeof(T) * VW) Vec { T v[VW]; };
+
+template <typename T, int VW>
+__device__ __forceinline__ Vec<T, VW> vload(const T* p) { return *reinterpret_cast<const Vec<T, VW>*>(p); }
+
+template <typename T, int VW>
+__device__ __forceinline__ Vec<T, VW> vzero() {
+  Vec<T, VW> z;
+#pragma unroll
+  for (int i = 0; i < VW; ++i) z.v[i] = (T)0;
+  return z;
+}
+
 struct ProjArgs {
   int a_slot;        // -1: the projectors B; else a psi-sized slot (overlap)
   int u_slot;        // right operand
-  int out_overlap;   // write partials to the same ppart buffer either way
+  int out_overlap;   // unused by the kernel (kept for the launch record)
 };
 
 // Items: (dom, p tile, j tile, split).  Block = 4 waves in 2 x 2, each wave a
 // (BM/2) x (BN/2) tile of 16 x 16 MFMA blocks.  KG grid points per LDS stage.
-template <typename TIn, typename TC, int BM, int BN, int KG>
+// VW: vector width of the global loads (row lengths 2 np and 2 n_orb must be
+// multiples of VW).
+template <typename TIn, typename TC, int BM, int BN, int KG, int VW>
 __global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ doms,
                                                     const Item* __restrict__ items, ProjArgs args) {
   constexpr int TM = BM / 32, TN = BN / 32;
   constexpr int LA = 2 * BM + 4, LB = BN + 4;          // padded LDS rows
-  __shared__ TC sA[KG * LA];
-  __shared__ TC sB[KG * LB];
+  constexpr int VA = KG * 2 * BM / VW, VB = KG * BN / VW;
+  constexpr int RA = (VA + kBlock - 1) / kBlock, RB = (VB + kBlock - 1) / kBlock;
+  __shared__ __align__(16) TC sA[KG * LA];
+  __shared__ __align__(16) TC sB[KG * LB];
 
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
@@ -71,6 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ 
 
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BN / 2);
+  const int ll = lane % 16, lk = lane / 16;
   using acc_t = typename Mfma<TC>::acc_t;
   acc_t acc[TM][TN];
 #pragma unroll
@@ -78,21 +101,51 @@ __global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ 
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  const int ll = lane % 16, lk = lane / 16;
-  for (long long gc = g_begin; gc < g_end; gc += KG) {
-    for (int idx = threadIdx.x; idx < KG * 2 * BM; idx += kBlock) {
-      const int gl = idx / (2 * BM), c = idx % (2 * BM);
+  Vec<TIn, VW> ra[RA], rb[RB];
+  auto load = [&](long long gc) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (2 * BM / VW), c = (idx % (2 * BM / VW)) * VW;
       const long long g = gc + gl;
       const int p2 = 2 * p0 + c;
-      sA[gl * LA + c] = (g < g_end && p2 < 2 * np) ? (TC)Bsrc[g * (2 * np) + p2] : (TC)0;
+      ra[q] = (idx < VA && g < g_end && p2 < 2 * np) ? vload<TIn, VW>(Bsrc + g * (2 * np) + p2) : vzero<TIn, VW>();
     }
-    for (int idx = threadIdx.x; idx < KG * BN; idx += kBlock) {
-      const int gl = idx / BN, c = idx % BN;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (BN / VW), c = (idx % (BN / VW)) * VW;
       const long long g = gc + gl;
       const int j = j0 + c;
-      sB[gl * LB + c] = (g < g_end && j < no2) ? (TC)U[g * no2 + j] : (TC)0;
+      rb[q] = (idx < VB && g < g_end && j < no2) ? vload<TIn, VW>(U + g * no2 + j) : vzero<TIn, VW>();
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int gl = idx / (2 * BM / VW), c = (idx % (2 * BM / VW)) * VW;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) sA[gl * LA + c + e] = (TC)ra[q].v[e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int gl = idx / (BN / VW), c = (idx % (BN / VW)) * VW;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) sB[gl * LB + c + e] = (TC)rb[q].v[e];
+      }
+    }
+  };
+
+  load(g_begin);
+  for (long long gc = g_begin; gc < g_end; gc += KG) {
+    store();
     __syncthreads();
+    if (gc + KG < g_end) load(gc + KG);
 #pragma unroll 2
     for (int ks = 0; ks < KG / 2; ++ks) {
       const int gl = 2 * ks + (lk >> 1), cc = lk & 1;
@@ -133,7 +186,7 @@ struct ReduceArgs {
 };
 
 // Items: (dom, block index over n_proj * n_orb pairs).  Deterministic: the
-// split-K partials are summed in split order.
+// split-K partials are summed in split order.  Q' rows are D.ldq apart.
 template <typename TC>
 __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ doms,
                                                    const Item* __restrict__ items, ReduceArgs args) {
@@ -170,10 +223,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
       const TC qr = sc * ((TC)args.cre * pr - (TC)args.cim * pi);
       const TC qi = sc * ((TC)args.cre * pi + (TC)args.cim * pr);
       TC* Q = (TC*)D.qmat;
-      Q[(long long)(2 * p) * no2 + 2 * n] = qr;
-      Q[(long long)(2 * p) * no2 + 2 * n + 1] = qi;
-      Q[(long long)(2 * p + 1) * no2 + 2 * n] = -qi;
-      Q[(long long)(2 * p + 1) * no2 + 2 * n + 1] = qr;
+      const long long ldq = D.ldq;
+      Q[(long long)(2 * p) * ldq + 2 * n] = qr;
+      Q[(long long)(2 * p) * ldq + 2 * n + 1] = qi;
+      Q[(long long)(2 * p + 1) * ldq + 2 * n] = -qi;
+      Q[(long long)(2 * p + 1) * ldq + 2 * n + 1] = qr;
       if (args.want_energy) e = (double)fn * (double)dp * ((double)pr * pr + (double)pi * pi);
       qmax = fmaxf(fabsf((float)qr), fabsf((float)qi));
     }
@@ -191,18 +245,24 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
 }
 
 // Items: (dom, g tile, j tile).  out_raw[g][j] += sum_k B_raw[g][k] Q'[k][j].
-// Block = 4 waves in 2 x 2; KC real reduction indices per LDS stage.
-template <typename TIn, typename TC, int BMG, int BN, int KC>
+// Block = 4 waves in 2 x 2; KC real reduction indices per LDS stage.  VW: load
+// width for the rows of B (2 n_proj must be a multiple of VW); Q' rows are
+// padded to a multiple of 4 elements (D.ldq) and zero in the padding.
+template <typename TIn, typename TC, int BMG, int BN, int KC, int VW>
 __global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ doms,
                                                     const Item* __restrict__ items, int out_slot) {
   constexpr int TM = BMG / 32, TN = BN / 32;
-  constexpr int LA = KC + 1, LB = BN + 4;
-  __shared__ TC sA[BMG * LA];
-  __shared__ TC sB[KC * LB];
+  constexpr int LA = KC + 2, LB = BN + 4;
+  constexpr int QW = 16 / sizeof(TC);                   // Q' vector width (rows padded)
+  constexpr int VA = BMG * KC / VW, VB = KC * BN / QW;
+  constexpr int RA = (VA + kBlock - 1) / kBlock, RB = (VB + kBlock - 1) / kBlock;
+  __shared__ __align__(16) TC sA[BMG * LA];
+  __shared__ __align__(16) TC sB[KC * LB];
 
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
   const int K = 2 * D.n_proj, no2 = 2 * D.n_orb;
+  const long long ldq = D.ldq;
   const long long g0 = (long long)it.a * BMG;
   const int j0 = it.b * BN;
   const TIn* __restrict__ Braw = (const TIn*)D.proj;
@@ -219,19 +279,50 @@ __global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ 
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int idx = threadIdx.x; idx < BMG * KC; idx += kBlock) {
-      const int r = idx / KC, c = idx % KC;
+  Vec<TIn, VW> ra[RA];
+  Vec<TC, QW> rb[RB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (KC / VW), c = (idx % (KC / VW)) * VW;
       const long long g = g0 + r;
       const int k = k0 + c;
-      sA[r * LA + c] = (g < D.n_grid && k < K) ? (TC)Braw[g * K + k] : (TC)0;
+      ra[q] = (idx < VA && g < D.n_grid && k < K) ? vload<TIn, VW>(Braw + g * K + k) : vzero<TIn, VW>();
     }
-    for (int idx = threadIdx.x; idx < KC * BN; idx += kBlock) {
-      const int r = idx / BN, c = idx % BN;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (BN / QW), c = (idx % (BN / QW)) * QW;
       const int k = k0 + r, j = j0 + c;
-      sB[r * LB + c] = (k < K && j < no2) ? Q[(long long)k * no2 + j] : (TC)0;
+      rb[q] = (idx < VB && k < K && j < ldq) ? vload<TC, QW>(Q + (long long)k * ldq + j) : vzero<TC, QW>();
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (KC / VW), c = (idx % (KC / VW)) * VW;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) sA[r * LA + c + e] = (TC)ra[q].v[e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int r = idx / (BN / QW), c = (idx % (BN / QW)) * QW;
+        *reinterpret_cast<Vec<TC, QW>*>(&sB[r * LB + c]) = rb[q];
+      }
+    }
+  };
+
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    store();
     __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);
 #pragma unroll 2
     for (int ks = 0; ks < KC / 4; ++ks) {
       TC a[TM], b[TN];

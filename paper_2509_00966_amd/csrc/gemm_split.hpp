@@ -7,7 +7,8 @@
 // (max |x| 2^s in [2^14, 2^15)) so both terms stay in FP16 range; the sums are
 // scaled back by 2^-(s_a + s_b).
 //
-// Operand storage (all 16-bit, hi and lo in separate planes):
+// Operand storage (all 16-bit, hi and lo in separate planes, rows padded with
+// zeros to a multiple of 8 halves so every tile row moves as 16-byte loads):
 //   Bs[g][k]   k = 2p + c : the projectors as stored (correction, A operand)
 //   Bt[p][k]   k = 2g + c : transposed (projection, A operand)
 //   Qt[j][k]   k = 2p + c : transposed real form of coef D P (correction, B operand)
@@ -96,7 +97,8 @@ __global__ void k_zero_maxbits(const DomDesc* __restrict__ doms, const Item* __r
 }
 
 // Pre-split of the projectors: Bs (natural layout) and Bt (transposed), hi and
-// lo.  Items: (dom, 32-row g tile, 32-column p tile).
+// lo, including the zero padding of both.  Items: (dom, 32-row g tile, 32-column
+// p tile); the tiles cover the padded extents.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_presplit(const DomDesc* __restrict__ doms, const Item* __restrict__ items) {
   using T = typename Half<MODE>::T;
@@ -113,28 +115,26 @@ __global__ __launch_bounds__(kBlock) void k_presplit(const DomDesc* __restrict__
     const long long g = g0 + r;
     const int k = 2 * p0 + c;
     float v = 0.f;
-    if (g < D.n_grid && k < k2) {
-      v = B[g * k2 + k];
+    if (g < D.n_grid && k < k2) v = B[g * k2 + k];
+    if (g < D.n_grid && k < D.ldbs) {
       T hi, lo;
       split2<MODE>(v, scale, hi, lo);
-      ((T*)D.bs_hi)[g * k2 + k] = hi;
-      ((T*)D.bs_lo)[g * k2 + k] = lo;
+      ((T*)D.bs_hi)[g * D.ldbs + k] = hi;
+      ((T*)D.bs_lo)[g * D.ldbs + k] = lo;
     }
     tile[r][c] = v;
   }
   __syncthreads();
-  // transposed: Bt[p][2g + c]
+  // transposed: Bt[p][2g + c]; the last g tile also clears the row padding
   for (int idx = threadIdx.x; idx < 32 * 64; idx += kBlock) {
     const int pr = idx / 64, q = idx % 64;      // q = 2 * g_local + c
-    const int gl = q / 2, c = q % 2;
     const int p = p0 + pr;
-    const long long g = g0 + gl;
-    if (p < np && g < D.n_grid) {
+    const long long k = 2 * g0 + q;
+    if (p < np && k < D.ldbt) {
       T hi, lo;
-      split2<MODE>(tile[gl][2 * pr + c], scale, hi, lo);
-      const long long o = (long long)p * (2 * D.n_grid) + 2 * g + c;
-      ((T*)D.bt_hi)[o] = hi;
-      ((T*)D.bt_lo)[o] = lo;
+      split2<MODE>(tile[q / 2][2 * pr + q % 2], scale, hi, lo);   // zero past N_g
+      ((T*)D.bt_hi)[(long long)p * D.ldbt + k] = hi;
+      ((T*)D.bt_lo)[(long long)p * D.ldbt + k] = lo;
     }
   }
 }
@@ -142,16 +142,20 @@ __global__ __launch_bounds__(kBlock) void k_presplit(const DomDesc* __restrict__
 // Projection partials: part[s][p][j] = sum over the split's grid points of the
 // real-form product, from Bt (16-bit, pre-split) and u (FP32, split here).
 // Items: (dom, p tile, j tile, split).  KG grid points (2 KG reduction indices)
-// per LDS stage; 2 KG must be a multiple of 32.
+// per LDS stage; 2 KG must be a multiple of 32.  Global tiles are prefetched
+// into registers one stage ahead.
 template <int MODE, int BM, int BN, int KG>
 __global__ __launch_bounds__(kBlock) void k_project_split(const DomDesc* __restrict__ doms,
-                                                          const Item* __restrict__ items,
-                                                          int u_slot) {
+                                                          const Item* __restrict__ items, int u_slot) {
   using T = typename Half<MODE>::T;
   using V8 = typename Half<MODE>::V8;
   constexpr int KK = 2 * KG;                 // reduction indices per stage
   constexpr int LK = KK + 8;                 // padded row (halves)
   constexpr int TM = BM / 32, TN = BN / 32;
+  constexpr int VA = BM * KK / 8;            // 16-byte vectors per plane of the A tile
+  constexpr int RA = (VA + kBlock - 1) / kBlock;
+  constexpr int VB = KG * BN / 2;            // complex values of the u tile
+  constexpr int RB = (VB + kBlock - 1) / kBlock;
   static_assert(KK % 32 == 0, "stage must hold whole MFMA steps");
   __shared__ __align__(16) T sAh[BM * LK];
   __shared__ __align__(16) T sAl[BM * LK];
@@ -161,11 +165,11 @@ __global__ __launch_bounds__(kBlock) void k_project_split(const DomDesc* __restr
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
   const int np = D.n_proj, no2 = 2 * D.n_orb;
-  const long long ng2 = 2 * D.n_grid;
+  const long long ldbt = D.ldbt;
   const int p0 = it.a * BM, j0 = it.b * BN;
   const long long g_begin = (long long)it.c * D.split_len;
   const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
-  const float* __restrict__ U = (const float*)D.slot[u_slot];
+  const float2* __restrict__ U = (const float2*)D.slot[u_slot];
   const T* __restrict__ bth = (const T*)D.bt_hi;
   const T* __restrict__ btl = (const T*)D.bt_lo;
   const float su = MODE == 1 ? fp16_scale_from_bits(D.maxbits[1]) : 1.0f;
@@ -180,34 +184,61 @@ __global__ __launch_bounds__(kBlock) void k_project_split(const DomDesc* __restr
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
-  for (long long gc = g_begin; gc < g_end; gc += KG) {
-    // A: rows p, reduction indices [2 gc, 2 gc + KK) of Bt
-    for (int idx = threadIdx.x; idx < BM * KK; idx += kBlock) {
-      const int r = idx / KK, q = idx % KK;
+  V8 rah[RA], ral[RA];
+  float2 rb[RB];
+  const V8 z8 = {};
+  auto load = [&](long long gc) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (KK / 8), c = (idx % (KK / 8)) * 8;
       const int p = p0 + r;
-      const long long k = 2 * gc + q;
-      const bool ok = p < np && k < 2 * g_end;
-      sAh[r * LK + q] = ok ? bth[(long long)p * ng2 + k] : (T)0.f;
-      sAl[r * LK + q] = ok ? btl[(long long)p * ng2 + k] : (T)0.f;
+      const long long k = 2 * gc + c;
+      const bool ok = idx < VA && p < np && k < 2 * g_end;   // rows are zero padded to ldbt
+      rah[q] = ok ? *(const V8*)(bth + (long long)p * ldbt + k) : z8;
+      ral[q] = ok ? *(const V8*)(btl + (long long)p * ldbt + k) : z8;
     }
-    // B: columns j, k = 2 g_local + c: c = 0 -> u[g][j], c = 1 -> (j even: u[g][j+1], j odd: -u[g][j-1])
-    for (int idx = threadIdx.x; idx < KG * (BN / 2); idx += kBlock) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
       const int gl = idx / (BN / 2), nn = idx % (BN / 2);
       const long long g = gc + gl;
       const int j = j0 + 2 * nn;
-      float re = 0.f, im = 0.f;
-      if (g < g_end && j < no2) {
-        re = U[g * no2 + j];
-        im = U[g * no2 + j + 1];
-      }
-      T rh, rl, ih, il;
-      split2<MODE>(re, su, rh, rl);
-      split2<MODE>(im, su, ih, il);
-      const int c0 = (2 * nn) * LK + 2 * gl, c1 = (2 * nn + 1) * LK + 2 * gl;
-      sBh[c0] = rh; sBh[c0 + 1] = ih; sBh[c1] = ih; sBh[c1 + 1] = (T)(-(float)rh);
-      sBl[c0] = rl; sBl[c0 + 1] = il; sBl[c1] = il; sBl[c1 + 1] = (T)(-(float)rl);
+      rb[q] = (idx < VB && g < g_end && j < no2) ? U[g * (no2 / 2) + j / 2] : make_float2(0.f, 0.f);
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (KK / 8), c = (idx % (KK / 8)) * 8;
+        *(V8*)&sAh[r * LK + c] = rah[q];
+        *(V8*)&sAl[r * LK + c] = ral[q];
+      }
+    }
+    // column j, k = 2 g_local + c: c = 0 -> u[g][j]; c = 1 -> (j even: u[g][j+1], j odd: -u[g][j-1])
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+        T rh, rl, ih, il;
+        split2<MODE>(rb[q].x, su, rh, rl);
+        split2<MODE>(rb[q].y, su, ih, il);
+        const T nrh = (T)(-(float)rh), nrl = (T)(-(float)rl);
+        const int c0 = (2 * nn) * LK + 2 * gl, c1 = (2 * nn + 1) * LK + 2 * gl;
+        sBh[c0] = rh; sBh[c0 + 1] = ih; sBh[c1] = ih; sBh[c1 + 1] = nrh;
+        sBl[c0] = rl; sBl[c0 + 1] = il; sBl[c1] = il; sBl[c1 + 1] = nrl;
+      }
+    }
+  };
+
+  load(g_begin);
+  for (long long gc = g_begin; gc < g_end; gc += KG) {
+    store();
     __syncthreads();
+    if (gc + KG < g_end) load(gc + KG);
 #pragma unroll
     for (int ks = 0; ks < KK / 32; ++ks) {
       V8 ah[TM], al[TM], bh[TN], bl[TN];
@@ -248,21 +279,23 @@ __global__ __launch_bounds__(kBlock) void k_project_split(const DomDesc* __restr
       }
 }
 
-// Q'^T hi/lo from the FP32 real form Q' (written by k_reduce).  FP16 mode uses
-// the max of |Q'| gathered with an atomic by the same k_reduce launch.
-// Items: (dom, block over 2 n_orb x 2 n_proj entries).
+// Q'^T hi/lo (rows of ldqt halves, zero padded) from the FP32 real form Q'
+// written by k_reduce.  FP16 mode uses the max of |Q'| gathered with an atomic
+// by the same k_reduce launch.  Items: (dom, block over 2 n_orb x ldqt entries).
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_split_q(const DomDesc* __restrict__ doms, const Item* __restrict__ items) {
   using T = typename Half<MODE>::T;
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
   const int k2 = 2 * D.n_proj, no2 = 2 * D.n_orb;
+  const long long ldqt = D.ldqt;
   const long long idx = (long long)it.a * kBlock + threadIdx.x;
-  if (idx >= (long long)k2 * no2) return;
-  const int j = (int)(idx / k2), k = (int)(idx % k2);
+  if (idx >= (long long)no2 * ldqt) return;
+  const int j = (int)(idx / ldqt), k = (int)(idx % ldqt);
   const float scale = MODE == 1 ? fp16_scale_from_bits(D.maxbits[2]) : 1.0f;
+  const float v = k < k2 ? ((const float*)D.qmat)[(long long)k * D.ldq + j] : 0.f;
   T hi, lo;
-  split2<MODE>(((const float*)D.qmat)[(long long)k * no2 + j], scale, hi, lo);
+  split2<MODE>(v, scale, hi, lo);
   ((T*)D.qt_hi)[idx] = hi;
   ((T*)D.qt_lo)[idx] = lo;
 }
@@ -271,12 +304,13 @@ __global__ __launch_bounds__(kBlock) void k_split_q(const DomDesc* __restrict__ 
 // Items: (dom, g tile, j tile).  KC reduction indices per LDS stage.
 template <int MODE, int BMG, int BN, int KC>
 __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restrict__ doms,
-                                                          const Item* __restrict__ items,
-                                                          int out_slot) {
+                                                          const Item* __restrict__ items, int out_slot) {
   using T = typename Half<MODE>::T;
   using V8 = typename Half<MODE>::V8;
   constexpr int LK = KC + 8;
   constexpr int TM = BMG / 32, TN = BN / 32;
+  constexpr int VA = BMG * KC / 8, VB = BN * KC / 8;
+  constexpr int RA = (VA + kBlock - 1) / kBlock, RB = (VB + kBlock - 1) / kBlock;
   static_assert(KC % 32 == 0, "stage must hold whole MFMA steps");
   __shared__ __align__(16) T sAh[BMG * LK];
   __shared__ __align__(16) T sAl[BMG * LK];
@@ -285,7 +319,8 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
 
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
-  const int K = 2 * D.n_proj, no2 = 2 * D.n_orb;
+  const long long ldbs = D.ldbs, ldqt = D.ldqt;
+  const int no2 = 2 * D.n_orb;
   const long long g0 = (long long)it.a * BMG;
   const int j0 = it.b * BN;
   const T* __restrict__ ah_g = (const T*)D.bs_hi;
@@ -303,23 +338,56 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int idx = threadIdx.x; idx < BMG * KC; idx += kBlock) {
-      const int r = idx / KC, q = idx % KC;
+  V8 rah[RA], ral[RA], rbh[RB], rbl[RB];
+  const V8 z8 = {};
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
       const long long g = g0 + r;
-      const int k = k0 + q;
-      const bool ok = g < D.n_grid && k < K;
-      sAh[r * LK + q] = ok ? ah_g[g * K + k] : (T)0.f;
-      sAl[r * LK + q] = ok ? al_g[g * K + k] : (T)0.f;
+      const int k = k0 + c;
+      const bool ok = idx < VA && g < D.n_grid && k < ldbs;
+      rah[q] = ok ? *(const V8*)(ah_g + g * ldbs + k) : z8;
+      ral[q] = ok ? *(const V8*)(al_g + g * ldbs + k) : z8;
     }
-    for (int idx = threadIdx.x; idx < BN * KC; idx += kBlock) {
-      const int r = idx / KC, q = idx % KC;
-      const int j = j0 + r, k = k0 + q;
-      const bool ok = j < no2 && k < K;
-      sBh[r * LK + q] = ok ? bh_g[(long long)j * K + k] : (T)0.f;
-      sBl[r * LK + q] = ok ? bl_g[(long long)j * K + k] : (T)0.f;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
+      const int j = j0 + r, k = k0 + c;
+      const bool ok = idx < VB && j < no2 && k < ldqt;
+      rbh[q] = ok ? *(const V8*)(bh_g + (long long)j * ldqt + k) : z8;
+      rbl[q] = ok ? *(const V8*)(bl_g + (long long)j * ldqt + k) : z8;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
+        *(V8*)&sAh[r * LK + c] = rah[q];
+        *(V8*)&sAl[r * LK + c] = ral[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
+        *(V8*)&sBh[r * LK + c] = rbh[q];
+        *(V8*)&sBl[r * LK + c] = rbl[q];
+      }
+    }
+  };
+
+  const int K = (int)ldbs;   // zero padded: the padding contributes nothing
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    store();
     __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);
 #pragma unroll
     for (int ks = 0; ks < KC / 32; ++ks) {
       V8 ah[TM], al[TM], bh[TN], bl[TN];
