@@ -52,6 +52,8 @@ struct DomDesc {
   int item0_stencil;            // first item of this domain in its stencil launch
   int item0_reduce;             // ... in its reduce launch
   int item0_elem;               // ... in its elementwise launch
+  int n_chunks;                 // orbital chunks of the stencil sweep
+  void* dpart;                  // [n_chunks][N_g][4] density / current partials
   // per-step observables (may be null)
   void* rho;                    // [.][N_g]
   void* jcur;                   // [.][N_g][3]

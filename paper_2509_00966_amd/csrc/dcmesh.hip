@@ -152,6 +152,7 @@ struct Plan {
   std::vector<Item> items;
   std::vector<Launch> stencil, proj, reduce, corr, dens, elem, energy, ovl_proj, ovl_reduce;
   std::vector<Launch> presplit, absmax_b, absmax_u, splitq;   // split-precision modes
+  std::vector<Launch> dfinish;                                 // density partials -> rho, j
   size_t bytes_tables = 0, bytes_total = 0;
   size_t off_items = 0, off_flag = 0;
   bool any_proj = false;
@@ -178,6 +179,25 @@ void group_launch(std::vector<Launch>& out, std::vector<Item>& items, int n_dom,
     L.count = (int)(items.size() - L.first);
     if (L.count > 0) out.push_back(L);
   }
+}
+
+// Reorders items [begin, end), made of consecutive clusters of cs items, so
+// that each cluster lands on one XCD: work-groups are dealt to the 8 XCDs
+// round-robin by index, so position t*8 + c of every run of 8 clusters goes to
+// XCD c.  Items of one cluster share operand rows (a split-K slice, or the
+// halo planes of one z segment), which then meet in that XCD's L2.
+void xcd_interleave(std::vector<Item>& items, size_t begin, size_t end, size_t cs) {
+  const size_t n = end - begin;
+  if (cs == 0 || n % cs) return;
+  const size_t nclus = n / cs;
+  std::vector<Item> out;
+  out.reserve(n);
+  for (size_t c0 = 0; c0 < nclus; c0 += 8) {
+    const size_t cn = std::min<size_t>(8, nclus - c0);
+    for (size_t t = 0; t < cs; ++t)
+      for (size_t c = 0; c < cn; ++c) out.push_back(items[begin + (c0 + c) * cs + t]);
+  }
+  std::copy(out.begin(), out.end(), items.begin() + begin);
 }
 
 // Builds the plan for these domains.  Pointers into the workspace are set when
@@ -225,12 +245,16 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
   group_launch(P.stencil, P.items, n_dom, sv,
                [&](int i, std::vector<Item>& it) {
                  const StencilVariant t = stile(sv(i));
-                 const DomDesc& D = P.desc[i];
+                 DomDesc& D = P.desc[i];
                  const int nzs = (int)cdiv(D.nz, D.zseg), nch = (int)cdiv(D.n_orb, t.oc);
+                 D.n_chunks = nch;
+                 const size_t b0 = it.size();
+                 const int nyt = (int)cdiv(D.ny, t.ty), nxt = (int)cdiv(D.nx, t.tx);
                  for (int zs = 0; zs < nzs; ++zs)
                    for (int ch = 0; ch < nch; ++ch)
-                     for (int yt = 0; yt < cdiv(D.ny, t.ty); ++yt)
-                       for (int xt = 0; xt < cdiv(D.nx, t.tx); ++xt) it.push_back({i, xt, yt, (zs << 16) | ch});
+                     for (int yt = 0; yt < nyt; ++yt)
+                       for (int xt = 0; xt < nxt; ++xt) it.push_back({i, xt, yt, (zs << 16) | ch});
+                 xcd_interleave(it, b0, it.size(), (size_t)nyt * nxt);
                },
                [&](int i, int first) { P.desc[i].item0_stencil = first; });
   for (const Launch& L : P.stencil)
@@ -240,9 +264,12 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
   group_launch(P.proj, P.items, n_dom, pv, [&](int i, std::vector<Item>& it) {
     const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i) % 4] : kProjF32[pv(i) % 4];
     const DomDesc& D = P.desc[i];
+    const size_t b0 = it.size();
+    const int nmt = (int)cdiv(D.n_proj, t.bm), nnt = (int)cdiv(2 * D.n_orb, t.bn);
     for (int s = 0; s < D.n_split; ++s)
-      for (int mt = 0; mt < cdiv(D.n_proj, t.bm); ++mt)
-        for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, mt, nt, s});
+      for (int mt = 0; mt < nmt; ++mt)
+        for (int nt = 0; nt < nnt; ++nt) it.push_back({i, mt, nt, s});
+    xcd_interleave(it, b0, it.size(), (size_t)nmt * nnt);
   });
   group_launch(P.reduce, P.items, n_dom, [&](int i) { return doms[i].n_proj > 0 ? 0 : -1; },
                [&](int i, std::vector<Item>& it) {
@@ -270,6 +297,9 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
                [&](int i, int first) { P.desc[i].item0_elem = first; });
   for (const Launch& L : P.elem)
     for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_g_part++;
+  group_launch(P.dfinish, P.items, n_dom, [](int) { return 0; }, [&](int i, std::vector<Item>& it) {
+    for (long long b = 0; b < cdiv(P.desc[i].n_grid, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
+  });
   group_launch(P.energy, P.items, n_dom, [](int) { return 0; },
                [&](int i, std::vector<Item>& it) { it.push_back({i, 0, 0, 0}); });
   // overlap S = h^3 Psi^H Psi (always FP64 arithmetic)
@@ -332,6 +362,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.e_loc = (double*)take(sizeof(double) * std::max(1, D.n_e_loc));
     D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
     D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
+    D.dpart = take((size_t)std::max(1, D.n_chunks) * D.n_grid * 4 * rs);
     if (is_split(prec) && D.n_proj > 0) {
       const size_t nbs = (size_t)D.n_grid * D.ldbs * 2, nbt = (size_t)D.n_proj * D.ldbt * 2;   // 16-bit values
       D.bs_hi = take(nbs); D.bs_lo = take(nbs);
@@ -649,7 +680,7 @@ void launch_correct_split(const Ctx& c, int out_slot) {
 // projector correction added in place).
 template <typename T>
 void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double cre, double cim,
-                 int occ_scale, int step, int want_energy) {
+                 int occ_scale, int step, int want_energy, int want_density = 0) {
   const int prec = c.P->prec;
   if (c.P->any_proj) {
     if (prec == DCMESH_SPLIT_BF16) {
@@ -662,7 +693,7 @@ void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double c
     }
     launch_reduce<T>(c, cre, cim, occ_scale, want_energy);
   }
-  StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy};
+  StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy, want_density};
   launch_stencil<T>(c, sa);
   if (c.P->any_proj) {
     if (prec == DCMESH_SPLIT_BF16)
@@ -684,6 +715,13 @@ template <typename T>
 void launch_density(const Ctx& c, int step, int obs) {
   ProfScope prof_(DCMESH_FAM_DENSITY, c.s);
   for (const Launch& L : c.P->dens) k_density<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, step, obs);
+}
+
+template <typename T>
+void launch_density_finish(const Ctx& c, int step, int obs) {
+  ProfScope prof_(DCMESH_FAM_DENSITY, c.s);
+  for (const Launch& L : c.P->dfinish)
+    k_density_finish<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, step, obs);
 }
 
 template <typename T>
@@ -743,8 +781,9 @@ int run_step(CallSetup& cs, int32_t n_steps, double dt, bool want_rho_j, bool wa
   const Ctx& c = cs.c;
   if (is_split(c.P->prec) && c.P->any_proj && n_steps > 0) launch_presplit(c);
   for (int k = 0; k < n_steps; ++k) {
-    if (want_rho_j) launch_density<T>(c, k, k);
-    apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0);
+    // stage 4 applies H to psi_k: it also yields E_k and the rho/j partials of psi_k
+    apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0, want_rho_j ? 1 : 0);
+    if (want_rho_j) launch_density_finish<T>(c, k, k);
     apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, k, 0);
     apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B0, 0.0, -dt / 2, 0, k, 0);
     apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_PSI, 0.0, -dt, 0, k, 0);

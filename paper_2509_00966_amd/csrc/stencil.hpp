@@ -8,9 +8,16 @@
 // marches along z over a segment of planes.  The z-neighbours of every owned
 // point-orbital sit in a register queue of 2r+1 planes; the x/y neighbours of
 // the centre plane are staged through LDS with an r-wide halo (only the star
-// arms, no corners).  Each u value leaves HBM about once per sweep plus the
-// halo strips, and the lanes of a wave touch OC consecutive orbitals of
-// consecutive points.
+// arms, no corners).  All global reads of plane z+1 (queue head, halo strips,
+// base values, potential) are issued before plane z is computed, so their
+// latency overlaps the arithmetic and stores of plane z.  Each u value leaves
+// HBM about once per sweep plus the halo strips, and the lanes of a wave touch
+// OC consecutive orbitals of consecutive points.
+//
+// With want_density the sweep also produces, per (grid point, orbital chunk),
+// the partial sums sum_n f_n |u_n|^2 and sum_n f_n Im(conj(u_n) D1_d u_n) of
+// the density and the paramagnetic current (reduced over the chunk's lanes
+// with shuffles); k_density_finish adds the chunks in order.
 #pragma once
 
 #include "common.hpp"
@@ -23,12 +30,14 @@ struct StencilArgs {
   int occ_scale;                    // multiply H_loc u by f_n
   int step;                         // A sample index
   int want_energy;                  // accumulate f_n Re(conj(u) H_loc u)
+  int want_density;                 // write density / current partials of u
 };
 
 template <typename T>
 struct StencilW {
   T alpha[3];       // -1/2 c_m / h^2, m = 1..r
-  T beta[3][3];     // A_d a_m / h
+  T a1[3];          // a_m / h
+  T A[3];           // vector potential
   T centre;         // -3/2 c_0 / h^2 + 1/2 |A|^2
 };
 
@@ -42,21 +51,13 @@ __device__ __forceinline__ StencilW<T> stencil_weights(const DomDesc& D, int ste
   for (int m = 1; m <= 3; ++m) {
     const bool on = m <= D.r;
     w.alpha[m - 1] = on ? (T)(-0.5 * fd2(D.r, m) * ih2) : (T)0;
-    w.beta[0][m - 1] = on ? (T)(a0 * fd1(D.r, m) * ih) : (T)0;
-    w.beta[1][m - 1] = on ? (T)(a1 * fd1(D.r, m) * ih) : (T)0;
-    w.beta[2][m - 1] = on ? (T)(a2 * fd1(D.r, m) * ih) : (T)0;
+    w.a1[m - 1] = on ? (T)(fd1(D.r, m) * ih) : (T)0;
   }
+  w.A[0] = (T)a0;
+  w.A[1] = (T)a1;
+  w.A[2] = (T)a2;
   w.centre = (T)(-1.5 * fd2(D.r, 0) * ih2 + 0.5 * (a0 * a0 + a1 * a1 + a2 * a2));
   return w;
-}
-
-// m-th neighbour pair along one axis: alpha (u+ + u-) - i beta (u+ - u-)
-template <typename T>
-__device__ __forceinline__ void pair_add(Cplx<T>& acc, Cplx<T> up, Cplx<T> um, T alpha, T beta) {
-  const T sr = up.re + um.re, si = up.im + um.im;
-  const T tr = up.re - um.re, ti = up.im - um.im;
-  acc.re += alpha * sr + beta * ti;
-  acc.im += alpha * si - beta * tr;
 }
 
 template <int R, int OC, int TX, int TY>
@@ -67,18 +68,38 @@ struct SweepCfg {
   static constexpr int kLX = TX + 2 * R;           // LDS plane with halo
   static constexpr int kLY = TY + 2 * R;
   static constexpr int kQ = 2 * R + 1;             // z queue depth
+  static constexpr int kHx = 2 * R * TY, kHy = 2 * R * TX, kH = kHx + kHy;   // halo columns
+  static constexpr int kHPer = (kH + kThrCols - 1) / kThrCols;               // halo columns per thread
   static_assert(kBlock % OC == 0 && kCols % kThrCols == 0, "tile does not fit the block");
 };
 
+// LDS coordinates of halo column hidx (x strips, then y strips).
+template <int R, int TX, int TY>
+__device__ __forceinline__ void halo_xy(int hidx, int& lx, int& ly) {
+  constexpr int kHx = 2 * R * TY;
+  if (hidx < kHx) {
+    const int side = hidx / (R * TY), rem = hidx % (R * TY);
+    ly = rem / R + R;
+    lx = side == 0 ? rem % R : TX + R + rem % R;
+  } else {
+    const int h2 = hidx - kHx;
+    const int side = h2 / (R * TX), rem = h2 % (R * TX);
+    lx = rem % TX + R;
+    ly = side == 0 ? rem / TX : TY + R + rem / TX;
+  }
+}
+
 // Items: (dom, x tile, y tile, (z segment << 16) | orbital chunk).
 // D.zseg planes per segment.  Energy partials: one per item, at
-// e_loc[blockIdx.x - D.item0_stencil].
+// e_loc[blockIdx.x - D.item0_stencil].  Density partials at
+// dpart[chunk][g][0..3] (rho, j_x, j_y, j_z without the A rho term).
 template <typename T, int R, int OC, int TX, int TY>
 __global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restrict__ doms,
                                                           const Item* __restrict__ items,
                                                           StencilArgs args) {
   using C = Cplx<T>;
   using Cfg = SweepCfg<R, OC, TX, TY>;
+  constexpr int KP = Cfg::kPer, KQ = Cfg::kQ, KH = Cfg::kHPer;
   __shared__ C lds[Cfg::kLY * Cfg::kLX * OC];
   __shared__ double red[4];
 
@@ -86,7 +107,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restr
   const DomDesc& D = doms[it.dom];
   const int nx = D.nx, ny = D.ny, nz = D.nz, no = D.n_orb;
   const int x0 = it.a * TX, y0 = it.b * TY;
-  const int zseg = it.c >> 16, oc0 = (it.c & 0xffff) * OC;
+  const int chunk = it.c & 0xffff;
+  const int zseg = it.c >> 16, oc0 = chunk * OC;
   const int z_begin = zseg * D.zseg, z_end = min(z_begin + D.zseg, nz);
 
   const C* __restrict__ u = (const C*)D.slot[args.u_slot];
@@ -103,14 +125,15 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restr
   const int n = oc0 + o;
   const bool n_ok = n < no;
   const T fn = n_ok ? occ[n] : (T)0;
+  const long long plane = (long long)nx * ny;
 
   // Columns of this thread.  Loads use wrapped coordinates so that slots past
   // the domain edge hold the periodic images needed by the last valid column.
-  int lxk[Cfg::kPer], lyk[Cfg::kPer];
-  long long gcol[Cfg::kPer];       // (y*nx + x) of the column, wrapped
-  bool ok[Cfg::kPer];
+  int lxk[KP], lyk[KP];
+  long long gcol[KP];
+  bool ok[KP];
 #pragma unroll
-  for (int k = 0; k < Cfg::kPer; ++k) {
+  for (int k = 0; k < KP; ++k) {
     const int col = tc + k * Cfg::kThrCols;
     lxk[k] = col % TX;
     lyk[k] = col / TX;
@@ -118,74 +141,151 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restr
     ok[k] = n_ok && x < nx && y < ny;
     gcol[k] = (long long)wrap(y, ny) * nx + wrap(x, nx);
   }
-  const long long plane = (long long)nx * ny;
+  // Halo columns of this thread
+  int hl[KH];
+  long long hcol[KH];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    const int hidx = tc + k * Cfg::kThrCols;
+    int lx = 0, ly = 0;
+    if (hidx < Cfg::kH) halo_xy<R, TX, TY>(hidx, lx, ly);
+    hl[k] = hidx < Cfg::kH ? (ly * Cfg::kLX + lx) * OC + o : -1;
+    hcol[k] = (long long)wrap(y0 + ly - R, ny) * nx + wrap(x0 + lx - R, nx);
+  }
 
-  C q[Cfg::kPer][Cfg::kQ];   // q[k][s] = plane z - R + s
+  auto ldu = [&](int z, long long col) -> C {
+    return n_ok ? u[((long long)z * plane + col) * no + n] : C{0, 0};
+  };
+
+  C q[KP][KQ];      // q[k][s] = plane z - R + s
+  C qn[KP];         // plane z + R + 1 (prefetch)
+  C hpf[KH];        // halo of plane z + 1 (prefetch)
+  C bcur[KP], bpf[KP];
+  T vcur[KP], vpf[KP];
+
+  // prologue: queue, centre plane of z_begin into LDS, its base and potential
 #pragma unroll
-  for (int k = 0; k < Cfg::kPer; ++k)
+  for (int k = 0; k < KP; ++k) {
 #pragma unroll
-    for (int s = 0; s < Cfg::kQ - 1; ++s) {
-      const int zz = wrap(z_begin - R + s, nz);
-      q[k][s + 1] = n_ok ? u[((long long)zz * plane + gcol[k]) * no + n] : C{0, 0};
-    }
+    for (int s = 0; s < KQ; ++s) q[k][s] = ldu(wrap(z_begin - R + s, nz), gcol[k]);
+    const long long g = (long long)z_begin * plane + gcol[k];
+    bcur[k] = (base && ok[k]) ? base[g * no + n] : C{0, 0};
+    vcur[k] = ok[k] ? V[g] : (T)0;
+    lds[((lyk[k] + R) * Cfg::kLX + (lxk[k] + R)) * OC + o] = q[k][R];
+  }
+#pragma unroll
+  for (int k = 0; k < KH; ++k)
+    if (hl[k] >= 0) lds[hl[k]] = ldu(z_begin, hcol[k]);
+  __syncthreads();
 
   double e_acc = 0.0;
   for (int z = z_begin; z < z_end; ++z) {
-    const int zf = wrap(z + R, nz);
+    const bool more = z + 1 < z_end;
+    if (more) {
+      const int zq = wrap(z + 1 + R, nz);
 #pragma unroll
-    for (int k = 0; k < Cfg::kPer; ++k) {
-#pragma unroll
-      for (int s = 0; s < Cfg::kQ - 1; ++s) q[k][s] = q[k][s + 1];
-      q[k][Cfg::kQ - 1] = n_ok ? u[((long long)zf * plane + gcol[k]) * no + n] : C{0, 0};
-      lds[((lyk[k] + R) * Cfg::kLX + (lxk[k] + R)) * OC + o] = q[k][R];
-    }
-    constexpr int kHx = 2 * R * TY, kHy = 2 * R * TX, kH = kHx + kHy;
-    for (int hidx = tc; hidx < kH; hidx += Cfg::kThrCols) {
-      int lx, ly;
-      if (hidx < kHx) {
-        const int side = hidx / (R * TY), rem = hidx % (R * TY);
-        ly = rem / R + R;
-        lx = side == 0 ? rem % R : TX + R + rem % R;
-      } else {
-        const int h2 = hidx - kHx;
-        const int side = h2 / (R * TX), rem = h2 % (R * TX);
-        lx = rem % TX + R;
-        ly = side == 0 ? rem / TX : TY + R + rem / TX;
+      for (int k = 0; k < KP; ++k) {
+        qn[k] = ldu(zq, gcol[k]);
+        const long long g1 = (long long)(z + 1) * plane + gcol[k];
+        bpf[k] = (base && ok[k]) ? base[g1 * no + n] : C{0, 0};
+        vpf[k] = ok[k] ? V[g1] : (T)0;
       }
-      const int xx = wrap(x0 + lx - R, nx), yy = wrap(y0 + ly - R, ny);
-      lds[(ly * Cfg::kLX + lx) * OC + o] =
-          n_ok ? u[(((long long)z * ny + yy) * nx + xx) * no + n] : C{0, 0};
+#pragma unroll
+      for (int k = 0; k < KH; ++k) hpf[k] = hl[k] >= 0 ? ldu(z + 1, hcol[k]) : C{0, 0};
     }
-    __syncthreads();
 
 #pragma unroll
-    for (int k = 0; k < Cfg::kPer; ++k) {
+    for (int k = 0; k < KP; ++k) {
       const int cx = lxk[k] + R, cy = lyk[k] + R;
       const C c0 = q[k][R];
-      const long long g = (long long)z * plane + gcol[k];
-      const T vg = ok[k] ? V[g] : (T)0;
-      C acc{(w.centre + vg) * c0.re, (w.centre + vg) * c0.im};
+      // per axis: S = sum_m alpha_m (u+ + u-), G = sum_m (a_m / h) (u+ - u-)
+      C S{0, 0}, G[3] = {{0, 0}, {0, 0}, {0, 0}};
 #pragma unroll
       for (int m = 1; m <= R; ++m) {
-        pair_add(acc, lds[(cy * Cfg::kLX + cx + m) * OC + o], lds[(cy * Cfg::kLX + cx - m) * OC + o],
-                 w.alpha[m - 1], w.beta[0][m - 1]);
-        pair_add(acc, lds[((cy + m) * Cfg::kLX + cx) * OC + o], lds[((cy - m) * Cfg::kLX + cx) * OC + o],
-                 w.alpha[m - 1], w.beta[1][m - 1]);
-        pair_add(acc, q[k][R + m], q[k][R - m], w.alpha[m - 1], w.beta[2][m - 1]);
+        const C xp = lds[(cy * Cfg::kLX + cx + m) * OC + o], xm = lds[(cy * Cfg::kLX + cx - m) * OC + o];
+        const C yp = lds[((cy + m) * Cfg::kLX + cx) * OC + o], ym = lds[((cy - m) * Cfg::kLX + cx) * OC + o];
+        const C zp = q[k][R + m], zm = q[k][R - m];
+        const T al = w.alpha[m - 1], am = w.a1[m - 1];
+        S.re += al * ((xp.re + xm.re) + (yp.re + ym.re) + (zp.re + zm.re));
+        S.im += al * ((xp.im + xm.im) + (yp.im + ym.im) + (zp.im + zm.im));
+        G[0].re += am * (xp.re - xm.re); G[0].im += am * (xp.im - xm.im);
+        G[1].re += am * (yp.re - ym.re); G[1].im += am * (yp.im - ym.im);
+        G[2].re += am * (zp.re - zm.re); G[2].im += am * (zp.im - zm.im);
+      }
+      // H_loc u = S - i A.G + (centre + V) c0
+      const T cv = w.centre + vcur[k];
+      C acc{S.re + cv * c0.re + (w.A[0] * G[0].im + w.A[1] * G[1].im + w.A[2] * G[2].im),
+            S.im + cv * c0.im - (w.A[0] * G[0].re + w.A[1] * G[1].re + w.A[2] * G[2].re)};
+      if (args.want_density) {
+        // f |c0|^2 and f Im(conj(c0) G_d), summed over the chunk's OC lanes
+        T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
+                   fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+        const int x = x0 + lxk[k], y = y0 + lyk[k];
+        if (o == 0 && x < nx && y < ny) {
+          const long long g = (long long)z * plane + gcol[k];
+          T* dp = (T*)D.dpart + ((long long)chunk * D.n_grid + g) * 4;
+          dp[0] = dv[0]; dp[1] = dv[1]; dp[2] = dv[2]; dp[3] = dv[3];
+        }
       }
       if (ok[k]) {
         if (args.want_energy) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
         if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
         C r{cre * acc.re - cim * acc.im, cre * acc.im + cim * acc.re};
-        if (base) { const C b = base[g * no + n]; r.re += b.re; r.im += b.im; }
+        r.re += bcur[k].re;
+        r.im += bcur[k].im;
+        const long long g = (long long)z * plane + gcol[k];
         out[g * no + n] = r;
       }
     }
+    if (!more) break;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+#pragma unroll
+      for (int s = 0; s < KQ - 1; ++s) q[k][s] = q[k][s + 1];
+      q[k][KQ - 1] = qn[k];
+      bcur[k] = bpf[k];
+      vcur[k] = vpf[k];
+      lds[((lyk[k] + R) * Cfg::kLX + (lxk[k] + R)) * OC + o] = q[k][R];
+    }
+#pragma unroll
+    for (int k = 0; k < KH; ++k)
+      if (hl[k] >= 0) lds[hl[k]] = hpf[k];
     __syncthreads();
   }
   if (args.want_energy) {
     const double s = block_sum(e_acc, red);
     if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+  }
+}
+
+// rho[g] = sum_chunks dpart[c][g][0];  j[g][d] = sum_chunks dpart[c][g][1 + d] + A_d rho.
+// Items: (dom, block of 256 grid points).  step: A sample; obs: output row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_density_finish(const DomDesc* __restrict__ doms,
+                                                           const Item* __restrict__ items, int step, int obs) {
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const long long g = (long long)it.a * kBlock + threadIdx.x;
+  if (g >= D.n_grid) return;
+  const int nch = D.n_chunks;
+  T s[4] = {0, 0, 0, 0};
+  for (int c = 0; c < nch; ++c) {
+    const T* dp = (const T*)D.dpart + ((long long)c * D.n_grid + g) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] += dp[i];
+  }
+  const double* A = D.a + (long long)step * D.a_stride;
+  if (D.rho) ((T*)D.rho)[(long long)obs * D.n_grid + g] = s[0];
+  if (D.jcur) {
+    T* j = (T*)D.jcur + ((long long)obs * D.n_grid + g) * 3;
+    j[0] = s[1] + (T)A[0] * s[0];
+    j[1] = s[2] + (T)A[1] * s[0];
+    j[2] = s[3] + (T)A[2] * s[0];
   }
 }
 
