@@ -63,6 +63,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "split_bf16", "split_fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="single", choices=["single", "batched"],
+                    help="single: the 64^3 domain (default); batched: 512 uneven domains, graph-replayed")
+    ap.add_argument("--graph-steps", type=int, default=100, help="steps captured per graph (batched)")
+    ap.add_argument("--autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the step has no cross-GPU part in this build "
@@ -72,6 +76,9 @@ def main():
     import torch
     import paper_2509_00966_amd as api
     from synth import config, pulse_midpoints
+
+    if args.workload == "batched":
+        return run_batched(args)
 
     log("bench: generating the 64^3 / 128-orbital / 512-projector domain")
     w = config(2)
@@ -110,24 +117,7 @@ def main():
     updates = ng * no * 4 * K / elapsed
     flops_gemm = 8.0 * ng * no * npj              # per projection or correction launch
     bytes_stencil = ng * no * 24.0 + ng * 4.0     # read u, read psi, write out, read V
-    kernels = {}
-    for fam, (ms, cnt) in prof.items():
-        if not cnt:
-            continue
-        avg = ms / cnt
-        entry = {"launches": cnt, "avg_ms": avg, "total_ms": ms}
-        if fam in ("project", "correct"):
-            entry.update(bound="mfma", achieved=flops_gemm / (avg * 1e-3) / 1e12, unit="TFLOP/s",
-                         peak=PEAK_TFLOPS[prec])
-        elif fam == "stencil":
-            entry.update(bound="hbm", achieved=bytes_stencil / (avg * 1e-3) / 1e9, unit="GB/s", peak=PEAK_HBM_GBS)
-        if "peak" in entry:
-            entry["frac"] = entry["achieved"] / entry["peak"]
-        kernels[fam] = entry
-    dom_fam = max((f for f in kernels if "peak" in kernels[f]), key=lambda f: kernels[f]["total_ms"])
-    dk = kernels[dom_fam]
-    roofline = {"kernel": dom_fam, "bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
-                "unit": dk["unit"], "frac": dk["frac"], "traffic": None}
+    roofline, kernels = roofline_of(prof, flops_gemm, bytes_stencil, prec)
 
     finite = bool(torch.isfinite(g.psi).all().item())
     cpu = None
@@ -155,6 +145,102 @@ def main():
         "s_per_orbital_step": elapsed / K / no,
         "psi_finite": finite,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def roofline_of(prof, flops_gemm, bytes_stencil, prec):
+    kernels = {}
+    for fam, (ms, cnt) in prof.items():
+        if not cnt:
+            continue
+        avg = ms / cnt
+        entry = {"launches": cnt, "avg_ms": avg, "total_ms": ms}
+        if fam in ("project", "correct"):
+            entry.update(bound="mfma", achieved=flops_gemm / (avg * 1e-3) / 1e12, unit="TFLOP/s",
+                         peak=PEAK_TFLOPS[prec])
+        elif fam == "stencil":
+            entry.update(bound="hbm", achieved=bytes_stencil / (avg * 1e-3) / 1e9, unit="GB/s", peak=PEAK_HBM_GBS)
+        if "peak" in entry:
+            entry["frac"] = entry["achieved"] / entry["peak"]
+        kernels[fam] = entry
+    dom_fam = max((f for f in kernels if "peak" in kernels[f]), key=lambda f: kernels[f]["total_ms"])
+    dk = kernels[dom_fam]
+    roof = {"kernel": dom_fam, "bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
+            "unit": dk["unit"], "frac": dk["frac"], "traffic": None}
+    return roof, kernels
+
+
+def run_batched(args):
+    """512 uneven domains (edge U{20..40}, orbitals U{16..96}, floor(N_o/4) atoms x 8
+    projectors, FD6, complex64), all advanced by one launch per kernel family
+    and Taylor stage; the steps are captured once in a HIP graph and replayed."""
+    import torch
+    import paper_2509_00966_amd as api
+    from synth import batched_domain, batched_domain_shapes, pulse_midpoints
+
+    prec = args.precision
+    cd, rd = api.complex_dtype(prec), api.real_dtype(prec)
+    dev = "cuda:0"
+    shapes = batched_domain_shapes()
+    log(f"bench: generating {len(shapes)} domains")
+    doms = []
+    t_gen = time.perf_counter()
+    for i in range(len(shapes)):
+        d = batched_domain(i)
+        t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x)).to(dev, dt)
+        doms.append(api.Domain(d.shape, d.fd_order, d.h, t(d.psi, cd), t(d.v_loc, rd), t(d.proj, cd),
+                               t(d.d, rd), t(d.occ, rd)))
+        if i % 64 == 63:
+            log(f"bench: {i + 1} domains on the GPU ({time.perf_counter() - t_gen:.0f} s)")
+    S = args.graph_steps
+    a_mid = pulse_midpoints(S, 0.02, S)
+    a_dev = torch.from_numpy(a_mid).to(dev)
+    ws = api.Workspace.for_domains(doms, prec)
+    log(f"bench: workspace {ws.nbytes / 2**30:.1f} GiB")
+    if args.autotune:
+        from paper_2509_00966_amd import autotune
+        best = autotune.tune(doms, a_dev, 0.02, prec)
+        autotune.apply(best)
+        log(f"bench: autotuned tiles {best}")
+    # one eager profiled step for the per-kernel breakdown
+    api.step(doms, a_dev[:1].contiguous(), 0.02, 1, prec, ws)
+    torch.cuda.synchronize()
+    api.profile_collect()
+    api.step(doms, a_dev[:1].contiguous(), 0.02, 1, prec, ws, profile=True)
+    prof = api.profile_collect()
+    log("bench: kernel times (1 eager step) " + json.dumps({k: [round(v[0], 3), v[1]] for k, v in prof.items() if v[1]}))
+    graph = api.Graph(doms, a_dev, 0.02, S, prec, ws)
+    graph.launch()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // S)
+    log(f"bench: timing {reps} graph replays of {S} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.launch()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    graph.close()
+    steps = reps * S
+    po = sum(d.n_grid * d.n_orb for d in doms)
+    flops_gemm = sum(8.0 * d.n_grid * d.n_orb * d.n_proj for d in doms)
+    bytes_stencil = sum(d.n_grid * d.n_orb * 24.0 + d.n_grid * 4.0 for d in doms)
+    roof, kernels = roofline_of(prof, flops_gemm, bytes_stencil, prec)
+    out = {
+        "metric": "orbital-gridpoint H.psi updates/s",
+        "value": po * 4 * steps / elapsed,
+        "unit": "orbital-gridpoint updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": S, "ms_per_step": elapsed * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "fp32", "fp64": "fp64", "split_bf16": "bf16x2+fp32", "split_fp16": "fp16x2+fp32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "512 uneven periodic domains, edge U{20..40}, orbitals U{16..96}, "
+                               "floor(N_o/4) atoms x 8 projectors, FD6, h=0.4, laser A_z(t), dt=0.02; "
+                               f"{S}-step HIP graph replays", "precision": prec,
+                   "point_orbitals": po, "domains": len(doms)},
+        "roofline": roof, "kernels": kernels,
+        "gen_seconds": time.perf_counter() - t_gen - elapsed,
     }
     print(json.dumps(out))
 

@@ -57,8 +57,9 @@ def apply_hloc(dom, A, u):
 
 
 def project(dom, u):
-    """P = h^3 B^H u, shape [N_p, N_o]."""
-    return dom.h ** 3 * (dom.proj.conj().T @ u)
+    """P = h^3 B^H u, shape [N_p, N_o], evaluated as h^3 (u^H B)^H so that the
+    (large) projector array is never copied."""
+    return dom.h ** 3 * (u.conj().T @ dom.proj).conj().T
 
 
 def apply_vnl(dom, u):
