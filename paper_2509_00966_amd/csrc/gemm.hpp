@@ -141,6 +141,15 @@ __global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ 
     }
   };
 
+  // Lane constants of the operand reads.  A: row wm0 + 16 i + ll, reduction
+  // index (g, c) with c = lk & 1.  X: for c = 0 column col of u; for c = 1 the
+  // partner column (col + 1 for a real part, col - 1 for an imaginary part,
+  // negated) -- col has the parity of ll since wn0 and 16 j are even.
+  const int cc = lk & 1;
+  const int a_off = 2 * (wm0 + ll) + cc;
+  const int b_off = wn0 + ll + (cc == 0 ? 0 : ((ll & 1) == 0 ? 1 : -1));
+  const TC b_sign = (cc == 1 && (ll & 1)) ? (TC)-1 : (TC)1;
+
   load(g_begin);
   for (long long gc = g_begin; gc < g_end; gc += KG) {
     store();
@@ -148,15 +157,12 @@ __global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ 
     if (gc + KG < g_end) load(gc + KG);
 #pragma unroll 2
     for (int ks = 0; ks < KG / 2; ++ks) {
-      const int gl = 2 * ks + (lk >> 1), cc = lk & 1;
+      const int gl = 2 * ks + (lk >> 1);
       TC a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = sA[gl * LA + 2 * (wm0 + i * 16 + ll) + cc];
+      for (int i = 0; i < TM; ++i) a[i] = sA[gl * LA + a_off + 2 * i * 16];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int col = wn0 + j * 16 + ll;
-        b[j] = cc == 0 ? sB[gl * LB + col] : ((col & 1) == 0 ? sB[gl * LB + col + 1] : -sB[gl * LB + col - 1]);
-      }
+      for (int j = 0; j < TN; ++j) b[j] = b_sign * sB[gl * LB + b_off + j * 16];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
