@@ -381,7 +381,7 @@ struct Staging {
   void* host = nullptr;
   size_t bytes = 0;
   hipEvent_t done = nullptr;
-  bool pinned_forever = false;   // referenced by a captured graph
+  int graph_refs = 0;            // captured graphs that read this buffer
   ~Staging() {
     if (done) (void)hipEventDestroy(done);
     if (host) (void)hipHostFree(host);
@@ -391,8 +391,11 @@ struct Staging {
 std::mutex g_stage_mu;
 std::map<std::pair<size_t, size_t>, std::shared_ptr<Staging>> g_stage;   // (hash, bytes) -> buffer
 
-// Finds or creates the pinned copy of the tables.  Allocation is not allowed
-// under stream capture, so graph creation calls this before capturing.
+// Finds or creates the pinned copy of the tables.  A buffer whose last copy
+// has completed and that no graph references is rewritten for new contents, so
+// repeated calls with changing pointers (chunked runs, the adjoint sweep) reuse
+// a handful of allocations.  Allocation is not allowed under stream capture,
+// so graph creation stages its tables before capturing.
 int get_staging(const Plan& P, bool capturing, std::shared_ptr<Staging>* out) {
   const size_t bytes = P.bytes_tables;
   std::vector<char> img(bytes, 0);
@@ -400,32 +403,41 @@ int get_staging(const Plan& P, bool capturing, std::shared_ptr<Staging>* out) {
   std::memcpy(img.data() + P.off_items, P.items.data(), sizeof(Item) * P.items.size());
   const size_t hsh = std::hash<std::string>()(std::string(img.data(), img.size()));
   std::shared_ptr<Staging> st;
-  {
-    std::lock_guard<std::mutex> lk(g_stage_mu);
-    auto itr = g_stage.find({hsh, bytes});
-    if (itr != g_stage.end() && std::memcmp(itr->second->host, img.data(), bytes) == 0) st = itr->second;
-    if (!st) {
-      // drop finished, unreferenced buffers before adding one
-      if (g_stage.size() > 64) {
-        for (auto e = g_stage.begin(); e != g_stage.end();) {
-          if (!e->second->pinned_forever && e->second.use_count() == 1 &&
-              (!e->second->done || hipEventQuery(e->second->done) == hipSuccess))
-            e = g_stage.erase(e);
-          else
-            ++e;
-        }
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  auto itr = g_stage.find({hsh, bytes});
+  if (itr != g_stage.end() && std::memcmp(itr->second->host, img.data(), bytes) == 0) st = itr->second;
+  if (!st) {
+    if (capturing)
+      return fail(DCMESH_ERR_UNSUPPORTED,
+                  "these tables were not staged before capture: use dcmesh_graph_create to record steps");
+    // reuse an idle buffer of sufficient size
+    for (auto e = g_stage.begin(); e != g_stage.end(); ++e) {
+      Staging& c = *e->second;
+      if (c.graph_refs == 0 && e->second.use_count() == 1 && c.bytes >= bytes &&
+          (!c.done || hipEventQuery(c.done) == hipSuccess)) {
+        st = e->second;
+        g_stage.erase(e);
+        break;
       }
-      if (capturing)
-        return fail(DCMESH_ERR_UNSUPPORTED,
-                    "these tables were not staged before capture: use dcmesh_graph_create to record steps");
+    }
+    if (!st) {
       st = std::make_shared<Staging>();
       HIPCHK(hipHostMalloc(&st->host, bytes, hipHostMallocDefault));
       st->bytes = bytes;
-      std::memcpy(st->host, img.data(), bytes);
       HIPCHK(hipEventCreateWithFlags(&st->done, hipEventDisableTiming));
-      g_stage[{hsh, bytes}] = st;
     }
-    if (capturing) st->pinned_forever = true;
+    std::memcpy(st->host, img.data(), bytes);
+    g_stage[{hsh, bytes}] = st;
+    // bound the number of idle buffers kept
+    if (g_stage.size() > 64) {
+      for (auto e = g_stage.begin(); e != g_stage.end() && g_stage.size() > 64;) {
+        if (e->second != st && e->second->graph_refs == 0 && e->second.use_count() == 1 &&
+            (!e->second->done || hipEventQuery(e->second->done) == hipSuccess))
+          e = g_stage.erase(e);
+        else
+          ++e;
+      }
+    }
   }
   *out = st;
   return DCMESH_OK;
@@ -1014,7 +1026,8 @@ int dcmesh_graph_create(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
                    s, pre);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_stage_mu);
-    pre.keep->pinned_forever = true;
+    pre.keep->graph_refs += 1;
+    g->keep = pre.keep;
   }
   CallSetup cs;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1022,14 +1035,20 @@ int dcmesh_graph_create(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
                  s, cs);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(s, &graph);
-  if (rc) {
+  if (rc || e != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
-    return rc;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g->keep->graph_refs -= 1;
+    return rc ? rc : fail(DCMESH_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   }
-  if (e != hipSuccess) return fail(DCMESH_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   g->graph = graph;
-  HIPCHK(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
-  g->keep = cs.keep;
+  const hipError_t ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g->keep->graph_refs -= 1;
+    return fail(DCMESH_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
   *graph_out = g.release();
   return DCMESH_OK;
 }
@@ -1046,6 +1065,10 @@ int dcmesh_graph_destroy(void* graph) {
   GraphHandle* g = (GraphHandle*)graph;
   if (g->exec) HIPCHK(hipGraphExecDestroy(g->exec));
   if (g->graph) HIPCHK(hipGraphDestroy(g->graph));
+  if (g->keep) {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    g->keep->graph_refs -= 1;
+  }
   delete g;
   return DCMESH_OK;
 }

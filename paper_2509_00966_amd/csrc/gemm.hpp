@@ -258,7 +258,10 @@ template <typename TIn, typename TC, int BMG, int BN, int KC, int VW>
 __global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ doms,
                                                     const Item* __restrict__ items, int out_slot) {
   constexpr int TM = BMG / 32, TN = BN / 32;
-  constexpr int LA = KC + 2, LB = BN + 4;
+  // LDS row pads: A rows of KC + 2 keep the 16 rows x 2 reduction indices of a
+  // half-wave on distinct banks; B rows of BN + 16 (FP32) put the two
+  // reduction rows of a half-wave 16 banks apart.
+  constexpr int LA = KC + 2, LB = BN + (sizeof(TC) == 4 ? 16 : 4);
   constexpr int QW = 16 / sizeof(TC);                   // Q' vector width (rows padded)
   constexpr int VA = BMG * KC / VW, VB = KC * BN / QW;
   constexpr int RA = (VA + kBlock - 1) / kBlock, RB = (VB + kBlock - 1) / kBlock;
