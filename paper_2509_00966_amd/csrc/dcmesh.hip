@@ -60,10 +60,10 @@ const StencilVariant kStencilF64[] = {{8, 16, 8}, {8, 8, 8}, {4, 16, 8}, {16, 8,
 constexpr int kNStencil = 4;
 
 struct GemmVariant { int bm, bn; };
-const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 64}};
+const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
 constexpr int kNProj = 4;
-const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 128}};
+const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
 constexpr int kNCorr = 4;
 constexpr int kProjKG = 16;
@@ -92,7 +92,7 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
   const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
-  return bigm ? (bign ? 0 : 3) : (bign ? 2 : 1);
+  return bigm ? (bign ? 0 : 1) : (bign ? 2 : 1);
 }
 int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
@@ -362,7 +362,9 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.e_loc = (double*)take(sizeof(double) * std::max(1, D.n_e_loc));
     D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
     D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
-    D.dpart = take((size_t)std::max(1, D.n_chunks) * D.n_grid * 4 * rs);
+    // sized for the smallest orbital chunk of any stencil variant, so the
+    // workspace does not depend on the tile choice
+    D.dpart = take((size_t)cdiv(D.n_orb, 4) * D.n_grid * 4 * rs);
     if (is_split(prec) && D.n_proj > 0) {
       const size_t nbs = (size_t)D.n_grid * D.ldbs * 2, nbt = (size_t)D.n_proj * D.ldbt * 2;   // 16-bit values
       D.bs_hi = take(nbs); D.bs_lo = take(nbs);
@@ -572,11 +574,11 @@ void launch_project(const Ctx& c, int u_slot) {
         case 0: k_project<T, T, 128, 128, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 1: k_project<T, T, 64, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 2: k_project<T, T, 64, 128, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        case 3: k_project<T, T, 128, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 3: k_project<T, T, 128, 256, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 4: k_project<T, T, 128, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 5: k_project<T, T, 64, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 6: k_project<T, T, 64, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        default: k_project<T, T, 128, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        default: k_project<T, T, 128, 256, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
       }
     } else {
       switch (L.variant) {
@@ -608,11 +610,11 @@ void launch_correct(const Ctx& c, int out_slot) {
         case 0: k_correct<T, T, 64, 256, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 1: k_correct<T, T, 64, 128, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 2: k_correct<T, T, 64, 64, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        case 3: k_correct<T, T, 128, 128, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 3: k_correct<T, T, 128, 256, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 4: k_correct<T, T, 64, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 5: k_correct<T, T, 64, 128, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 6: k_correct<T, T, 64, 64, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        default: k_correct<T, T, 128, 128, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        default: k_correct<T, T, 128, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       }
     } else {
       switch (L.variant) {
@@ -664,7 +666,7 @@ void launch_project_split(const Ctx& c, int u_slot) {
       case 0: k_project_split<MODE, 128, 128, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 1: k_project_split<MODE, 64, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 2: k_project_split<MODE, 64, 128, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
-      default: k_project_split<MODE, 128, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      default: k_project_split<MODE, 128, 256, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
     }
   }
 }
@@ -683,7 +685,7 @@ void launch_correct_split(const Ctx& c, int out_slot) {
       case 0: k_correct_split<MODE, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       case 1: k_correct_split<MODE, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       case 2: k_correct_split<MODE, 64, 64, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      default: k_correct_split<MODE, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      default: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
     }
   }
 }

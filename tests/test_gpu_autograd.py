@@ -50,9 +50,15 @@ def test_gradient_matches_oracle(api, precision, ckpt):
     a_mid = np.zeros((n, 3))
     a_mid[:, 2] = az
     l_ref, g_ref = ADJ.loss_and_grad(od, a_mid, dt, od.psi, dirs=(2,))
-    tol = {"fp64": 1e-10, "fp32": 1e-4, "split_bf16": 1e-3}[precision]
-    assert abs(loss - l_ref) <= tol * abs(l_ref) + 1e-12
-    assert np.linalg.norm(grad - g_ref[:, 2]) <= tol * np.linalg.norm(g_ref[:, 2])
+    # The loss is a small difference of two energies: in the FP32 paths its
+    # error is set by the energy's own rounding, so it is compared on the
+    # energy's scale; the gradient is compared directly.
+    from oracle import observables as O
+    e_scale = abs(O.energy(od, np.zeros(3), od.psi))
+    tol_l = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-5}[precision]
+    tol_g = {"fp64": 1e-10, "fp32": 1e-4, "split_bf16": 1e-3}[precision]
+    assert abs(loss - l_ref) <= tol_l * e_scale
+    assert np.linalg.norm(grad - g_ref[:, 2]) <= tol_g * np.linalg.norm(g_ref[:, 2])
 
 
 def test_reduced_gradient_workload_fp32_vs_oracle(api):

@@ -17,7 +17,7 @@ from synth import config, make_domain, pulse_midpoints
 
 pytestmark = pytest.mark.gpu
 
-TOL_OP = {"fp64": 1e-12, "fp32": 2e-6}
+TOL_OP = {"fp64": 1e-12, "fp32": 5e-6}
 TOL_PSI = {"fp64": 1e-11, "fp32": 1e-5}
 
 
