@@ -337,11 +337,27 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     });
   }
 
-  // workspace layout
+  // Workspace layout.  The item tables get room for the largest item count
+  // any tile variant could produce (smallest tiles: stencil 8 x 4 columns x
+  // 4 orbitals over segments of >= min(nz, 16) planes; projector products in
+  // 32 x 32 tiles), so the workspace size does not depend on the tuning.
+  size_t variable = 0, bound = 0;
+  for (const auto* fam : {&P.stencil, &P.proj, &P.corr})
+    for (const Launch& L : *fam) variable += L.count;
+  for (int i = 0; i < n_dom; ++i) {
+    const DomDesc& D = P.desc[i];
+    const long long nzs = cdiv(D.nz, std::min(D.nz, 16));
+    bound += (size_t)(cdiv(D.nx, 8) * cdiv(D.ny, 4) * cdiv(D.n_orb, 4) * nzs);
+    if (D.n_proj > 0) {
+      bound += (size_t)(D.n_split * cdiv(D.n_proj, 32) * cdiv(2 * D.n_orb, 32));
+      bound += (size_t)(cdiv(D.n_grid, 32) * cdiv(2 * D.n_orb, 32));
+    }
+  }
+  const size_t item_room = P.items.size() - variable + std::max(bound, variable);
   size_t off = 0;
   off += align_up(sizeof(DomDesc) * n_dom);
   P.off_items = off;
-  off += align_up(sizeof(Item) * P.items.size());
+  off += align_up(sizeof(Item) * item_room);
   P.off_flag = off;
   off += kAlign;
   P.bytes_tables = off;
