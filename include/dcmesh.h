@@ -178,8 +178,12 @@ int dcmesh_graph_destroy(void* graph);
 
 /* Tile choices: dcmesh_set_tuning selects a kernel variant for a kernel family
  * (DCMESH_KERNEL_*) and value (see dcmesh_tuning_options); -1 restores the
- * built-in heuristic.  Process-wide; takes effect for calls made afterwards. */
-enum dcmesh_kernel { DCMESH_KERNEL_STENCIL = 0, DCMESH_KERNEL_PROJECT = 1, DCMESH_KERNEL_CORRECT = 2 };
+ * built-in heuristic.  Process-wide; takes effect for calls made afterwards.
+ * DCMESH_KERNEL_ZSEG picks the z-segment length of the stencil sweep (0: from
+ * the block count; 1..4: 8, 16, 32 planes, whole columns).  The workspace size
+ * does not depend on these choices. */
+enum dcmesh_kernel { DCMESH_KERNEL_STENCIL = 0, DCMESH_KERNEL_PROJECT = 1, DCMESH_KERNEL_CORRECT = 2,
+                     DCMESH_KERNEL_ZSEG = 3 };
 int dcmesh_set_tuning(int32_t kernel, int32_t variant);
 int dcmesh_tuning_options(int32_t kernel, int32_t* count);
 

@@ -21,7 +21,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 FLAG_CHECK_FINITE = 0x1
 FLAG_PROFILE = 0x2
 FAMILIES = ("stencil", "project", "reduce", "correct", "density", "energy", "adjoint", "overlap", "split")
-KERNEL = {"stencil": 0, "project": 1, "correct": 2}
+KERNEL = {"stencil": 0, "project": 1, "correct": 2, "zseg": 3}
 
 EXPORTS = (
     "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_density", "dcmesh_adjoint_step",

@@ -102,15 +102,17 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Sum over a 256-thread block; result valid in thread 0.
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* lds4) {
+// Sum over a block of NW waves (lds holds NW values); result valid in
+// thread 0, added in wave order.
+template <typename T, int NW = kBlock / kWave>
+__device__ __forceinline__ T block_sum(T v, T* lds) {
   v = wave_sum(v);
   const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) lds4[w] = v;
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
   __syncthreads();
   T s = 0;
-  if (threadIdx.x == 0) s = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NW; ++i) s += lds[i];
   __syncthreads();
   return s;
 }

@@ -54,10 +54,16 @@ size_t real_size(int prec) { return is_fp64(prec) ? 8 : 4; }
 // ---------------------------------------------------------------------------
 // Tile variants and tuning overrides
 // ---------------------------------------------------------------------------
-struct StencilVariant { int oc, tx, ty; };
-const StencilVariant kStencilF32[] = {{16, 16, 8}, {8, 16, 8}, {16, 8, 8}, {4, 16, 16}};
-const StencilVariant kStencilF64[] = {{8, 16, 8}, {8, 8, 8}, {4, 16, 8}, {16, 8, 4}};
-constexpr int kNStencil = 4;
+struct StencilVariant { int oc, tx, ty, nt; };
+const StencilVariant kStencilF32[] = {{16, 16, 8, 256}, {8, 16, 8, 256}, {16, 8, 8, 256},
+                                      {4, 16, 16, 256}, {16, 8, 8, 512}, {16, 16, 8, 512}};
+const StencilVariant kStencilF64[] = {{8, 16, 8, 256}, {8, 8, 8, 256}, {4, 16, 8, 256},
+                                      {16, 8, 4, 256}, {8, 8, 8, 512}, {8, 16, 8, 512}};
+constexpr int kNStencil = 6;
+constexpr int kStencilDefault = 2;
+// z planes per sweep segment: 0 = chosen from the block count, else fixed
+const int kZsegOpt[] = {0, 8, 16, 32, 1 << 20};
+constexpr int kNZseg = 5;
 
 struct GemmVariant { int bm, bn; };
 const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
@@ -68,11 +74,11 @@ const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
 constexpr int kNCorr = 4;
 constexpr int kProjKG = 16;
 
-std::atomic<int> g_tune[3] = {{-1}, {-1}, {-1}};
+std::atomic<int> g_tune[4] = {{-1}, {-1}, {-1}, {-1}};
 
 int stencil_variant(const dcmesh_domain&, int) {
   const int t = g_tune[DCMESH_KERNEL_STENCIL].load();
-  return t >= 0 ? t : 0;
+  return t >= 0 ? t : kStencilDefault;
 }
 // FP32 projector products load rows with 16-byte vectors when every row
 // length is a multiple of 4 floats, else with 8-byte (one complex) vectors;
@@ -212,8 +218,8 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
 
   // work lists
   // stencil launches are keyed by (radius, tile variant): variant + 4 r
-  auto sv = [&](int i) { return stencil_variant(doms[i], prec) + 4 * (doms[i].fd_order / 2); };
-  auto stile = [&](int v) { return is_fp64(prec) ? kStencilF64[v % 4] : kStencilF32[v % 4]; };
+  auto sv = [&](int i) { return stencil_variant(doms[i], prec) + 8 * (doms[i].fd_order / 2); };
+  auto stile = [&](int v) { return is_fp64(prec) ? kStencilF64[v % 8] : kStencilF32[v % 8]; };
   long long stencil_blocks_xy = 0;
   for (int i = 0; i < n_dom; ++i) {
     const StencilVariant t = stile(sv(i));
@@ -227,9 +233,15 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.n_orb = d.n_orb; D.n_proj = d.n_proj;
     D.n_grid = (long long)d.nx * d.ny * d.nz;
     D.h = d.h;
-    // z segments: aim at >= 1024 stencil blocks in total, segments of >= 16 planes
-    const long long want = std::max<long long>(1, cdiv(1024, std::max<long long>(1, stencil_blocks_xy)));
-    D.zseg = (int)std::min<long long>(d.nz, std::max<long long>(16, cdiv(d.nz, want)));
+    // z segments: aim at >= 1024 stencil blocks in total, segments of >= 16
+    // planes (or the tuned fixed length)
+    const int zt = g_tune[DCMESH_KERNEL_ZSEG].load();
+    if (zt > 0) {
+      D.zseg = std::min(d.nz, kZsegOpt[zt]);
+    } else {
+      const long long want = std::max<long long>(1, cdiv(1024, std::max<long long>(1, stencil_blocks_xy)));
+      D.zseg = (int)std::min<long long>(d.nz, std::max<long long>(16, cdiv(d.nz, want)));
+    }
     // split-K length depends on the domain alone, so a domain gives the same
     // bits whether it runs alone or inside a batch
     D.split_len = (int)std::min<long long>(2048, std::max<long long>(512, cdiv(cdiv(D.n_grid, 32), kProjKG) * kProjKG));
@@ -544,33 +556,37 @@ struct Ctx {
 template <typename T, int R>
 void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
   const Item* it = c.d_items + L.first;
-  const dim3 g(L.count), b(kBlock);
+  const dim3 g(L.count);
   if constexpr (sizeof(T) == 4) {
     switch (L.variant) {
-      case 0: k_stencil_sweep<T, R, 16, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-      case 1: k_stencil_sweep<T, R, 8, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-      case 2: k_stencil_sweep<T, R, 16, 8, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep<T, R, 4, 16, 16><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      case 0: k_stencil_sweep<T, R, 16, 16, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 1: k_stencil_sweep<T, R, 8, 16, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 2: k_stencil_sweep<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 3: k_stencil_sweep<T, R, 4, 16, 16, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 4: k_stencil_sweep<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep<T, R, 16, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
     }
   } else {
     switch (L.variant) {
-      case 0: k_stencil_sweep<T, R, 8, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-      case 1: k_stencil_sweep<T, R, 8, 8, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-      case 2: k_stencil_sweep<T, R, 4, 16, 8><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep<T, R, 16, 8, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+      case 0: k_stencil_sweep<T, R, 8, 16, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 1: k_stencil_sweep<T, R, 8, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 2: k_stencil_sweep<T, R, 4, 16, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 3: k_stencil_sweep<T, R, 16, 8, 4, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 4: k_stencil_sweep<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep<T, R, 8, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
     }
   }
 }
 
-// Stencil launches are keyed by variant + 4 r, so every domain of a launch
+// Stencil launches are keyed by variant + 8 r, so every domain of a launch
 // shares the stencil radius.
 template <typename T>
 void launch_stencil(const Ctx& c, const StencilArgs& a) {
   ProfScope prof_(DCMESH_FAM_STENCIL, c.s);
   for (const Launch& L : c.P->stencil) {
     Launch l2 = L;
-    l2.variant = L.variant % 4;
-    switch (L.variant / 4) {
+    l2.variant = L.variant % 8;
+    switch (L.variant / 8) {
       case 1: launch_stencil_r<T, 1>(c, l2, a); break;
       case 2: launch_stencil_r<T, 2>(c, l2, a); break;
       default: launch_stencil_r<T, 3>(c, l2, a); break;
@@ -1130,6 +1146,7 @@ int dcmesh_tuning_options(int32_t kernel, int32_t* count) {
     case DCMESH_KERNEL_STENCIL: *count = kNStencil; return DCMESH_OK;
     case DCMESH_KERNEL_PROJECT: *count = kNProj; return DCMESH_OK;
     case DCMESH_KERNEL_CORRECT: *count = kNCorr; return DCMESH_OK;
+    case DCMESH_KERNEL_ZSEG: *count = kNZseg; return DCMESH_OK;
     default: return fail(DCMESH_ERR_INVALID_ARGUMENT, "unknown kernel family");
   }
 }

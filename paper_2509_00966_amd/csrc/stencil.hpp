@@ -60,17 +60,17 @@ __device__ __forceinline__ StencilW<T> stencil_weights(const DomDesc& D, int ste
   return w;
 }
 
-template <int R, int OC, int TX, int TY>
+template <int R, int OC, int TX, int TY, int NT>
 struct SweepCfg {
   static constexpr int kCols = TX * TY;            // (x, y) columns per tile
-  static constexpr int kThrCols = kBlock / OC;     // columns covered by one pass of the block
+  static constexpr int kThrCols = NT / OC;         // columns covered by one pass of the block
   static constexpr int kPer = kCols / kThrCols;    // columns per thread
   static constexpr int kLX = TX + 2 * R;           // LDS plane with halo
   static constexpr int kLY = TY + 2 * R;
   static constexpr int kQ = 2 * R + 1;             // z queue depth
   static constexpr int kHx = 2 * R * TY, kHy = 2 * R * TX, kH = kHx + kHy;   // halo columns
   static constexpr int kHPer = (kH + kThrCols - 1) / kThrCols;               // halo columns per thread
-  static_assert(kBlock % OC == 0 && kCols % kThrCols == 0, "tile does not fit the block");
+  static_assert(NT % OC == 0 && kCols % kThrCols == 0, "tile does not fit the block");
 };
 
 // LDS coordinates of halo column hidx (x strips, then y strips).
@@ -93,15 +93,15 @@ __device__ __forceinline__ void halo_xy(int hidx, int& lx, int& ly) {
 // D.zseg planes per segment.  Energy partials: one per item, at
 // e_loc[blockIdx.x - D.item0_stencil].  Density partials at
 // dpart[chunk][g][0..3] (rho, j_x, j_y, j_z without the A rho term).
-template <typename T, int R, int OC, int TX, int TY>
-__global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restrict__ doms,
-                                                          const Item* __restrict__ items,
-                                                          StencilArgs args) {
+template <typename T, int R, int OC, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_stencil_sweep(const DomDesc* __restrict__ doms,
+                                                      const Item* __restrict__ items,
+                                                      StencilArgs args) {
   using C = Cplx<T>;
-  using Cfg = SweepCfg<R, OC, TX, TY>;
+  using Cfg = SweepCfg<R, OC, TX, TY, NT>;
   constexpr int KP = Cfg::kPer, KQ = Cfg::kQ, KH = Cfg::kHPer;
   __shared__ C lds[Cfg::kLY * Cfg::kLX * OC];
-  __shared__ double red[4];
+  __shared__ double red[NT / kWave];
 
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restr
   // Columns of this thread.  Loads use wrapped coordinates so that slots past
   // the domain edge hold the periodic images needed by the last valid column.
   int lxk[KP], lyk[KP];
-  long long gcol[KP];
+  int gcol[KP];                    // y * nx + x of the column (N_g < 2^31)
   bool ok[KP];
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -139,21 +139,21 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restr
     lyk[k] = col / TX;
     const int x = x0 + lxk[k], y = y0 + lyk[k];
     ok[k] = n_ok && x < nx && y < ny;
-    gcol[k] = (long long)wrap(y, ny) * nx + wrap(x, nx);
+    gcol[k] = wrap(y, ny) * nx + wrap(x, nx);
   }
   // Halo columns of this thread
   int hl[KH];
-  long long hcol[KH];
+  int hcol[KH];
 #pragma unroll
   for (int k = 0; k < KH; ++k) {
     const int hidx = tc + k * Cfg::kThrCols;
     int lx = 0, ly = 0;
     if (hidx < Cfg::kH) halo_xy<R, TX, TY>(hidx, lx, ly);
     hl[k] = hidx < Cfg::kH ? (ly * Cfg::kLX + lx) * OC + o : -1;
-    hcol[k] = (long long)wrap(y0 + ly - R, ny) * nx + wrap(x0 + lx - R, nx);
+    hcol[k] = wrap(y0 + ly - R, ny) * nx + wrap(x0 + lx - R, nx);
   }
 
-  auto ldu = [&](int z, long long col) -> C {
+  auto ldu = [&](int z, int col) -> C {
     return n_ok ? u[((long long)z * plane + col) * no + n] : C{0, 0};
   };
 
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sweep(const DomDesc* __restr
     __syncthreads();
   }
   if (args.want_energy) {
-    const double s = block_sum(e_acc, red);
+    const double s = block_sum<double, NT / kWave>(e_acc, red);
     if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
   }
 }
