@@ -70,6 +70,9 @@ const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
 constexpr int kNProj = 4;
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
+// split-precision kernels (variant 2 of each stages twice as much per LDS pass)
+const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}};
+const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
 constexpr int kNCorr = 4;
 constexpr int kProjKG = 16;
@@ -274,7 +277,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
 
   auto pv = [&](int i) { return doms[i].n_proj > 0 ? proj_variant(doms[i], prec) : -1; };
   group_launch(P.proj, P.items, n_dom, pv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i) % 4] : kProjF32[pv(i) % 4];
+    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i) % 4] : is_split(prec) ? kProjSplit[pv(i) % 4] : kProjF32[pv(i) % 4];
     const DomDesc& D = P.desc[i];
     const size_t b0 = it.size();
     const int nmt = (int)cdiv(D.n_proj, t.bm), nnt = (int)cdiv(2 * D.n_orb, t.bn);
@@ -293,7 +296,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_e_nl++;
   auto cv = [&](int i) { return doms[i].n_proj > 0 ? corr_variant(doms[i], prec) : -1; };
   group_launch(P.corr, P.items, n_dom, cv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i) % 4] : kCorrF32[cv(i) % 4];
+    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i) % 4] : is_split(prec) ? kCorrSplit[cv(i) % 4] : kCorrF32[cv(i) % 4];
     const DomDesc& D = P.desc[i];
     for (long long gt = 0; gt < cdiv(D.n_grid, t.bm); ++gt)
       for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, (int)gt, nt, 0});
@@ -697,7 +700,7 @@ void launch_project_split(const Ctx& c, int u_slot) {
     switch (L.variant) {
       case 0: k_project_split<MODE, 128, 128, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 1: k_project_split<MODE, 64, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
-      case 2: k_project_split<MODE, 64, 128, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      case 2: k_project_split<MODE, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       default: k_project_split<MODE, 128, 256, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
     }
   }
@@ -716,7 +719,7 @@ void launch_correct_split(const Ctx& c, int out_slot) {
     switch (L.variant) {
       case 0: k_correct_split<MODE, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       case 1: k_correct_split<MODE, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      case 2: k_correct_split<MODE, 64, 64, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      case 2: k_correct_split<MODE, 64, 256, 64><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       default: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
     }
   }

@@ -42,6 +42,9 @@ template <> struct Half<1> {   // FP16
   }
 };
 
+// Two adjacent 16-bit values moved as one 4-byte store.
+template <typename T> struct alignas(4) Pair { T a, b; };
+
 // hi/lo of x * 2^s (s = 0 for BF16)
 template <int MODE>
 __device__ __forceinline__ void split2(float x, float scale, typename Half<MODE>::T& hi, typename Half<MODE>::T& lo) {
@@ -217,7 +220,9 @@ __global__ __launch_bounds__(kBlock) void k_project_split(const DomDesc* __restr
         *(V8*)&sAl[r * LK + c] = ral[q];
       }
     }
-    // column j, k = 2 g_local + c: c = 0 -> u[g][j]; c = 1 -> (j even: u[g][j+1], j odd: -u[g][j-1])
+    // column j, k = 2 g_local + c: c = 0 -> u[g][j]; c = 1 -> (j even: u[g][j+1], j odd: -u[g][j-1]);
+    // the two reduction indices of a grid point are adjacent, so each column
+    // receives one 4-byte pair per plane
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
       const int idx = threadIdx.x + q * kBlock;
@@ -228,8 +233,10 @@ __global__ __launch_bounds__(kBlock) void k_project_split(const DomDesc* __restr
         split2<MODE>(rb[q].y, su, ih, il);
         const T nrh = (T)(-(float)rh), nrl = (T)(-(float)rl);
         const int c0 = (2 * nn) * LK + 2 * gl, c1 = (2 * nn + 1) * LK + 2 * gl;
-        sBh[c0] = rh; sBh[c0 + 1] = ih; sBh[c1] = ih; sBh[c1 + 1] = nrh;
-        sBl[c0] = rl; sBl[c0 + 1] = il; sBl[c1] = il; sBl[c1 + 1] = nrl;
+        *(Pair<T>*)&sBh[c0] = Pair<T>{rh, ih};
+        *(Pair<T>*)&sBh[c1] = Pair<T>{ih, nrh};
+        *(Pair<T>*)&sBl[c0] = Pair<T>{rl, il};
+        *(Pair<T>*)&sBl[c1] = Pair<T>{il, nrl};
       }
     }
   };
