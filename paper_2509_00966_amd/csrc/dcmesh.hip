@@ -100,6 +100,7 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
+  if (is_split(prec)) return d.n_proj >= 96 ? 0 : 1;
   const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
   return bigm ? (bign ? 0 : 1) : (bign ? 2 : 1);
 }
@@ -107,6 +108,7 @@ int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
+  if (is_split(prec)) return 2 * d.n_orb > 128 ? 0 : 1;
   const int n2 = 2 * d.n_orb;
   return n2 > 128 ? 0 : (n2 > 64 ? 1 : 2);
 }
