@@ -42,6 +42,8 @@ struct DomDesc {
   void* pmat;                   // [n_proj][2 n_orb]  P = h^3 B^H u
   void* qmat;                   // [2 n_proj][ldq] real form of coef D P
   long long ldq;                // row stride of qmat: 2 n_orb rounded up to 4
+  void* qmat3;                  // FP32: [3][n_proj][ldq3] Re Q, Im Q - Re Q, Re Q + Im Q (null otherwise)
+  long long ldq3;               // n_orb rounded up to 4
   double* e_loc;                // [n_stencil_items] local-energy partials
   double* e_nl;                 // [n_reduce_items] nonlocal-energy partials
   double* g_part;               // [n_grad_items][3] gradient partials

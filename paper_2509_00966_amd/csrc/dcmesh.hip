@@ -66,6 +66,8 @@ const int kZsegOpt[] = {0, 8, 16, 32, 1 << 20};
 constexpr int kNZseg = 5;
 
 struct GemmVariant { int bm, bn; };
+// FP32 variant 0 of each product is the three-product (Gauss) kernel; its tile
+// in complex orbitals is half the real-column tile listed here.
 const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
 constexpr int kNProj = 4;
@@ -253,6 +255,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.n_split = (int)cdiv(D.n_grid, D.split_len);
     D.a_stride = 3;
     D.ldq = (2 * D.n_orb + 3) / 4 * 4;
+    D.ldq3 = (D.n_orb + 3) / 4 * 4;
     D.ldbs = D.ldqt = (2 * (long long)D.n_proj + 7) / 8 * 8;
     D.ldbt = (2 * D.n_grid + 7) / 8 * 8;
   }
@@ -392,6 +395,8 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.ppart = take(part);
     D.pmat = take((size_t)D.n_proj * no2 * acc);
     D.qmat = take(2 * (size_t)D.n_proj * D.ldq * acc);
+    // three-product (Gauss) planes of coef D P for the FP32 correction
+    D.qmat3 = prec == DCMESH_FP32 ? take(3 * (size_t)D.n_proj * D.ldq3 * sizeof(float)) : nullptr;
     D.e_loc = (double*)take(sizeof(double) * std::max(1, D.n_e_loc));
     D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
     D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
@@ -608,11 +613,11 @@ void launch_project(const Ctx& c, int u_slot) {
     const dim3 g(L.count), b(kBlock);
     if constexpr (sizeof(T) == 4) {
       switch (L.variant) {
-        case 0: k_project<T, T, 128, 128, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 0: k_project3m<128, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 1: k_project<T, T, 64, 64, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 2: k_project<T, T, 64, 128, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 3: k_project<T, T, 128, 256, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        case 4: k_project<T, T, 128, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 4: k_project3m<128, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 5: k_project<T, T, 64, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 6: k_project<T, T, 64, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         default: k_project<T, T, 128, 256, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
@@ -644,11 +649,11 @@ void launch_correct(const Ctx& c, int out_slot) {
     const dim3 g(L.count), b(kBlock);
     if constexpr (sizeof(T) == 4) {
       switch (L.variant) {
-        case 0: k_correct<T, T, 64, 256, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 0: k_correct3m<64, 128, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 1: k_correct<T, T, 64, 128, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 2: k_correct<T, T, 64, 64, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 3: k_correct<T, T, 128, 256, 32, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        case 4: k_correct<T, T, 64, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 4: k_correct3m<64, 128, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 5: k_correct<T, T, 64, 128, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 6: k_correct<T, T, 64, 64, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         default: k_correct<T, T, 128, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;

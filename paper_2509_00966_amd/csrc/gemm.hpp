@@ -234,6 +234,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
       Q[(long long)(2 * p) * ldq + 2 * n + 1] = qi;
       Q[(long long)(2 * p + 1) * ldq + 2 * n] = -qi;
       Q[(long long)(2 * p + 1) * ldq + 2 * n + 1] = qr;
+      if (D.qmat3) {
+        TC* Q3 = (TC*)D.qmat3;
+        const long long pl = (long long)np * D.ldq3;
+        Q3[(long long)p * D.ldq3 + n] = qr;
+        Q3[pl + (long long)p * D.ldq3 + n] = qi - qr;
+        Q3[2 * pl + (long long)p * D.ldq3 + n] = qr + qi;
+      }
       if (args.want_energy) e = (double)fn * (double)dp * ((double)pr * pr + (double)pi * pi);
       qmax = fmaxf(fabsf((float)qr), fabsf((float)qi));
     }
@@ -357,6 +364,263 @@ __global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ 
         if (g < D.n_grid && jj < no2) {
           TIn* o = out + g * no2 + jj;
           *o = (TIn)((TC)*o + acc[i][j][r]);
+        }
+      }
+}
+
+}  // namespace dcm
+
+namespace dcm {
+
+// ---------------------------------------------------------------------------
+// FP32 projector products with three real products per complex product
+// (Gauss's form), on the complex operands as stored:
+//   (a + ib)(c + id):  k1 = c (a + b'), k2 = a (d - c), k3 = b' (c + d),
+//                      Re = k1 - k3, Im = k1 + k2   (b' = b, or -b for conj(a + ib)).
+// Projection P = B^H u: a = Re B, b' = -Im B, c = Re u, d = Im u.
+// Correction B Q:       a = Re B, b' =  Im B, c = Re Q, d = Im Q, with the
+// three combinations of Q stored by the reduce kernel as planes
+// Q3[0] = Re Q, Q3[1] = Im Q - Re Q, Q3[2] = Re Q + Im Q.
+// Each complex multiply-add costs 6 real flops on MFMA instead of 8.
+// ---------------------------------------------------------------------------
+
+// Items: (dom, p tile, complex-orbital tile, split).  Block = 4 waves in 2 x 2,
+// wave tile (BM/2) projectors x (BNC/2) orbitals; KG grid points per LDS stage.
+template <int BM, int BNC, int KG, int VW>
+__global__ __launch_bounds__(kBlock) void k_project3m(const DomDesc* __restrict__ doms,
+                                                      const Item* __restrict__ items, ProjArgs args) {
+  constexpr int TM = BM / 32, TN = BNC / 32;
+  constexpr int LA = 2 * BM + 8, LB = 2 * BNC + 8;
+  constexpr int VA = KG * 2 * BM / VW, VB = KG * 2 * BNC / VW;
+  constexpr int RA = (VA + kBlock - 1) / kBlock, RB = (VB + kBlock - 1) / kBlock;
+  __shared__ __align__(16) float sA[KG * LA];
+  __shared__ __align__(16) float sB[KG * LB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no = D.n_orb, no2 = 2 * no;
+  const float* __restrict__ Bsrc = (const float*)D.proj;
+  const float* __restrict__ U = (const float*)D.slot[args.u_slot];
+  const int p0 = it.a * BM, n0 = it.b * BNC;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BNC / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 k1[TM][TN], k2[TM][TN], k3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) k1[i][j] = k2[i][j] = k3[i][j] = f32x4{0, 0, 0, 0};
+
+  Vec<float, VW> ra[RA], rb[RB];
+  auto load = [&](long long gc) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (2 * BM / VW), c = (idx % (2 * BM / VW)) * VW;
+      const long long g = gc + gl;
+      const int p2 = 2 * p0 + c;
+      ra[q] = (idx < VA && g < g_end && p2 < 2 * np) ? vload<float, VW>(Bsrc + g * (2 * np) + p2) : vzero<float, VW>();
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (2 * BNC / VW), c = (idx % (2 * BNC / VW)) * VW;
+      const long long g = gc + gl;
+      const int j = 2 * n0 + c;
+      rb[q] = (idx < VB && g < g_end && j < no2) ? vload<float, VW>(U + g * no2 + j) : vzero<float, VW>();
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int gl = idx / (2 * BM / VW), c = (idx % (2 * BM / VW)) * VW;
+        *reinterpret_cast<Vec<float, VW>*>(&sA[gl * LA + c]) = ra[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int gl = idx / (2 * BNC / VW), c = (idx % (2 * BNC / VW)) * VW;
+        *reinterpret_cast<Vec<float, VW>*>(&sB[gl * LB + c]) = rb[q];
+      }
+    }
+  };
+
+  load(g_begin);
+  for (long long gc = g_begin; gc < g_end; gc += KG) {
+    store();
+    __syncthreads();
+    if (gc + KG < g_end) load(gc + KG);
+#pragma unroll 2
+    for (int ks = 0; ks < KG / 4; ++ks) {
+      const int gl = 4 * ks + lk;
+      float a1[TM], a2[TM], a3[TM], b1[TN], b2[TN], b3[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const float2 v = *reinterpret_cast<const float2*>(&sA[gl * LA + 2 * (wm0 + i * 16 + ll)]);
+        a1[i] = v.x - v.y;   // a + b' with b' = -Im B
+        a2[i] = v.x;
+        a3[i] = -v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const float2 v = *reinterpret_cast<const float2*>(&sB[gl * LB + 2 * (wn0 + j * 16 + ll)]);
+        b1[j] = v.x;
+        b2[j] = v.y - v.x;
+        b3[j] = v.x + v.y;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          k1[i][j] = Mfma<float>::run(a1[i], b1[j], k1[i][j]);
+          k2[i][j] = Mfma<float>::run(a2[i], b2[j], k2[i][j]);
+          k3[i][j] = Mfma<float>::run(a3[i], b3[j], k3[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  float* __restrict__ part = (float*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + wm0 + i * 16 + 4 * lk + r;
+        const int n = n0 + wn0 + j * 16 + ll;
+        if (p < np && n < no)
+          *reinterpret_cast<float2*>(&part[(long long)p * no2 + 2 * n]) =
+              make_float2(k1[i][j][r] - k3[i][j][r], k1[i][j][r] + k2[i][j][r]);
+      }
+}
+
+// Items: (dom, g tile, complex-orbital tile).  out[g][n] += sum_p B[g][p] Q[p][n]
+// with Q from the three planes D.qmat3 (rows of D.ldq3 floats).  Block = 4
+// waves in 2 x 2, wave tile (BMG/2) grid points x (BNC/2) orbitals; KC
+// projectors per LDS stage.
+template <int BMG, int BNC, int KC, int VW>
+__global__ __launch_bounds__(kBlock) void k_correct3m(const DomDesc* __restrict__ doms,
+                                                      const Item* __restrict__ items, int out_slot) {
+  constexpr int TM = BMG / 32, TN = BNC / 32;
+  constexpr int LA = 2 * KC + 2, LB = BNC + 16;
+  constexpr int VA = BMG * 2 * KC / VW, VB = 3 * KC * BNC / 4;
+  constexpr int RA = (VA + kBlock - 1) / kBlock, RB = (VB + kBlock - 1) / kBlock;
+  __shared__ __align__(16) float sA[BMG * LA];
+  __shared__ __align__(16) float sB[3 * KC * LB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no = D.n_orb, K2 = 2 * np;
+  const long long ldq3 = D.ldq3;
+  const long long g0 = (long long)it.a * BMG;
+  const int n0 = it.b * BNC;
+  const float* __restrict__ Braw = (const float*)D.proj;
+  const float* __restrict__ Q3 = (const float*)D.qmat3;
+  float* __restrict__ out = (float*)D.slot[out_slot];
+
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wm0 = (wv / 2) * (BMG / 2), wn0 = (wv % 2) * (BNC / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 k1[TM][TN], k2[TM][TN], k3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) k1[i][j] = k2[i][j] = k3[i][j] = f32x4{0, 0, 0, 0};
+
+  Vec<float, VW> ra[RA];
+  Vec<float, 4> rb[RB];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (2 * KC / VW), c = (idx % (2 * KC / VW)) * VW;
+      const long long g = g0 + r;
+      const int k = 2 * p0 + c;
+      ra[q] = (idx < VA && g < D.n_grid && k < K2) ? vload<float, VW>(Braw + g * K2 + k) : vzero<float, VW>();
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int row = idx / (BNC / 4), c = (idx % (BNC / 4)) * 4;   // row = plane * KC + p_local
+      const int pl = row / KC, p = p0 + row % KC, n = n0 + c;
+      rb[q] = (idx < VB && p < np && n < ldq3) ? vload<float, 4>(Q3 + ((long long)pl * np + p) * ldq3 + n)
+                                               : vzero<float, 4>();
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (2 * KC / VW), c = (idx % (2 * KC / VW)) * VW;
+#pragma unroll
+        for (int e = 0; e < VW; e += 2)
+          *reinterpret_cast<float2*>(&sA[r * LA + c + e]) = make_float2(ra[q].v[e], ra[q].v[e + 1]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int row = idx / (BNC / 4), c = (idx % (BNC / 4)) * 4;
+        *reinterpret_cast<Vec<float, 4>*>(&sB[row * LB + c]) = rb[q];
+      }
+    }
+  };
+
+  load(0);
+  for (int p0 = 0; p0 < np; p0 += KC) {
+    store();
+    __syncthreads();
+    if (p0 + KC < np) load(p0 + KC);
+#pragma unroll 2
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int pl = 4 * ks + lk;
+      float a1[TM], a2[TM], a3[TM], b1[TN], b2[TN], b3[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const float2 v = *reinterpret_cast<const float2*>(&sA[(wm0 + i * 16 + ll) * LA + 2 * pl]);
+        a1[i] = v.x + v.y;
+        a2[i] = v.x;
+        a3[i] = v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn0 + j * 16 + ll;
+        b1[j] = sB[(0 * KC + pl) * LB + n];
+        b2[j] = sB[(1 * KC + pl) * LB + n];
+        b3[j] = sB[(2 * KC + pl) * LB + n];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          k1[i][j] = Mfma<float>::run(a1[i], b1[j], k1[i][j]);
+          k2[i][j] = Mfma<float>::run(a2[i], b2[j], k2[i][j]);
+          k3[i][j] = Mfma<float>::run(a3[i], b3[j], k3[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int n = n0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && n < no) {
+          float2* o = reinterpret_cast<float2*>(out + (g * no + n) * 2);
+          const float2 prev = *o;
+          *o = make_float2(prev.x + (k1[i][j][r] - k3[i][j][r]), prev.y + (k1[i][j][r] + k2[i][j][r]));
         }
       }
 }
