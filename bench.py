@@ -166,7 +166,10 @@ def roofline_of(prof, flops_gemm, bytes_stencil, prec, bytes_gemm=None):
     three 16-bit products per real product, so their MFMA work is 3x that.
     bytes_gemm: compulsory bytes of one such launch (projectors once, orbitals
     once), used when it, not the MFMA work, bounds the launch."""
-    split = prec.startswith("split")
+    # MFMA work per launch relative to the complex-product count 8 N_g N_o N_p:
+    # FP32 runs the three-real-product (Gauss) form (6 flops per complex
+    # multiply-add), split modes three 16-bit products per real product.
+    mfma_factor = {"fp32": 0.75, "fp64": 1.0, "split_bf16": 3.0, "split_fp16": 3.0}[prec]
     kernels = {}
     for fam, (ms, cnt) in prof.items():
         if not cnt:
@@ -174,7 +177,7 @@ def roofline_of(prof, flops_gemm, bytes_stencil, prec, bytes_gemm=None):
         avg = ms / cnt
         entry = {"launches": cnt, "avg_ms": avg, "total_ms": ms}
         if fam in ("project", "correct"):
-            mfma_flops = flops_gemm * (3 if split else 1)
+            mfma_flops = flops_gemm * mfma_factor
             t_mfma = mfma_flops / (PEAK_TFLOPS[prec] * 1e12)
             t_hbm = (bytes_gemm or 0) / (PEAK_HBM_GBS * 1e9)
             entry["algorithmic_tflops"] = flops_gemm / (avg * 1e-3) / 1e12
