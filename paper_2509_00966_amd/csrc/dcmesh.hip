@@ -55,11 +55,14 @@ size_t real_size(int prec) { return is_fp64(prec) ? 8 : 4; }
 // Tile variants and tuning overrides
 // ---------------------------------------------------------------------------
 struct StencilVariant { int oc, tx, ty, nt; };
+// variants 6 and 7 prefetch two planes ahead with a double-buffered LDS plane
 const StencilVariant kStencilF32[] = {{16, 16, 8, 256}, {8, 16, 8, 256}, {16, 8, 8, 256},
-                                      {4, 16, 16, 256}, {16, 8, 8, 512}, {16, 16, 8, 512}};
+                                      {4, 16, 16, 256}, {16, 8, 8, 512}, {16, 16, 8, 512},
+                                      {16, 8, 8, 512}, {16, 8, 8, 256}};
 const StencilVariant kStencilF64[] = {{8, 16, 8, 256}, {8, 8, 8, 256}, {4, 16, 8, 256},
-                                      {16, 8, 4, 256}, {8, 8, 8, 512}, {8, 16, 8, 512}};
-constexpr int kNStencil = 6;
+                                      {16, 8, 4, 256}, {8, 8, 8, 512}, {8, 16, 8, 512},
+                                      {8, 8, 8, 512}, {8, 8, 8, 256}};
+constexpr int kNStencil = 8;
 constexpr int kStencilDefault = 2;
 // z planes per sweep segment: 0 = chosen from the block count, else fixed
 const int kZsegOpt[] = {0, 8, 16, 32, 1 << 20};
@@ -574,7 +577,9 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
       case 2: k_stencil_sweep<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
       case 3: k_stencil_sweep<T, R, 4, 16, 16, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
       case 4: k_stencil_sweep<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep<T, R, 16, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 5: k_stencil_sweep<T, R, 16, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 6: k_stencil_sweep2<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep2<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
     }
   } else {
     switch (L.variant) {
@@ -583,7 +588,9 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
       case 2: k_stencil_sweep<T, R, 4, 16, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
       case 3: k_stencil_sweep<T, R, 16, 8, 4, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
       case 4: k_stencil_sweep<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep<T, R, 8, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 5: k_stencil_sweep<T, R, 8, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 6: k_stencil_sweep2<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep2<T, R, 8, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
     }
   }
 }

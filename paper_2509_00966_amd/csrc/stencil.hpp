@@ -263,6 +263,183 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep(const DomDesc* __restrict_
   }
 }
 
+// Same sweep with the global reads issued two planes ahead and the centre
+// plane double-buffered in LDS (one barrier per plane).  The plane loop is
+// unrolled by two so the two prefetch register sets are addressed statically.
+template <typename T, int R, int OC, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_stencil_sweep2(const DomDesc* __restrict__ doms,
+                                                       const Item* __restrict__ items,
+                                                       StencilArgs args) {
+  using C = Cplx<T>;
+  using Cfg = SweepCfg<R, OC, TX, TY, NT>;
+  constexpr int KP = Cfg::kPer, KQ = Cfg::kQ, KH = Cfg::kHPer;
+  constexpr int PLANE = Cfg::kLY * Cfg::kLX * OC;
+  __shared__ C lds[2 * PLANE];
+  __shared__ double red[NT / kWave];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int nx = D.nx, ny = D.ny, nz = D.nz, no = D.n_orb;
+  const int x0 = it.a * TX, y0 = it.b * TY;
+  const int chunk = it.c & 0xffff;
+  const int zseg = it.c >> 16, oc0 = chunk * OC;
+  const int z_begin = zseg * D.zseg, z_end = min(z_begin + D.zseg, nz);
+
+  const C* __restrict__ u = (const C*)D.slot[args.u_slot];
+  const C* __restrict__ base = args.base_slot < SLOT_NONE ? (const C*)D.slot[args.base_slot] : nullptr;
+  C* __restrict__ out = (C*)D.slot[args.out_slot];
+  const T* __restrict__ V = (const T*)D.v;
+  const T* __restrict__ occ = (const T*)D.occ;
+
+  const StencilW<T> w = stencil_weights<T>(D, args.step);
+  const T cre = (T)args.cre, cim = (T)args.cim;
+
+  const int o = threadIdx.x % OC;
+  const int tc = threadIdx.x / OC;
+  const int n = oc0 + o;
+  const bool n_ok = n < no;
+  const T fn = n_ok ? occ[n] : (T)0;
+  const long long plane = (long long)nx * ny;
+
+  int lxk[KP], lyk[KP], gcol[KP];
+  bool ok[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int col = tc + k * Cfg::kThrCols;
+    lxk[k] = col % TX;
+    lyk[k] = col / TX;
+    const int x = x0 + lxk[k], y = y0 + lyk[k];
+    ok[k] = n_ok && x < nx && y < ny;
+    gcol[k] = wrap(y, ny) * nx + wrap(x, nx);
+  }
+  int hl[KH], hcol[KH];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    const int hidx = tc + k * Cfg::kThrCols;
+    int lx = 0, ly = 0;
+    if (hidx < Cfg::kH) halo_xy<R, TX, TY>(hidx, lx, ly);
+    hl[k] = hidx < Cfg::kH ? (ly * Cfg::kLX + lx) * OC + o : -1;
+    hcol[k] = wrap(y0 + ly - R, ny) * nx + wrap(x0 + lx - R, nx);
+  }
+  auto ldu = [&](int z, int col) -> C {
+    return n_ok ? u[((long long)z * plane + col) * no + n] : C{0, 0};
+  };
+
+  struct Pf {   // everything plane z needs that is not already in the queue
+    C qh[KP];   // queue head: plane z + R
+    C h[KH];    // halo of plane z
+    C b[KP];    // base of plane z
+    T v[KP];    // potential of plane z
+  };
+  auto fetch = [&](Pf& f, int z) {
+    const int zq = wrap(z + R, nz);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      f.qh[k] = ldu(zq, gcol[k]);
+      const long long g = (long long)z * plane + gcol[k];
+      f.b[k] = (base && ok[k]) ? base[g * no + n] : C{0, 0};
+      f.v[k] = ok[k] ? V[g] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < KH; ++k) f.h[k] = hl[k] >= 0 ? ldu(z, hcol[k]) : C{0, 0};
+  };
+
+  C q[KP][KQ];       // q[k][s] = plane z - R + s
+  C bcur[KP];
+  T vcur[KP];
+  // prologue: queue of z_begin, its centre plane and halo in LDS buffer 0
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+#pragma unroll
+    for (int s = 0; s < KQ; ++s) q[k][s] = ldu(wrap(z_begin - R + s, nz), gcol[k]);
+    const long long g = (long long)z_begin * plane + gcol[k];
+    bcur[k] = (base && ok[k]) ? base[g * no + n] : C{0, 0};
+    vcur[k] = ok[k] ? V[g] : (T)0;
+    lds[((lyk[k] + R) * Cfg::kLX + (lxk[k] + R)) * OC + o] = q[k][R];
+  }
+#pragma unroll
+  for (int k = 0; k < KH; ++k)
+    if (hl[k] >= 0) lds[hl[k]] = ldu(z_begin, hcol[k]);
+  Pf pa, pb;
+  if (z_begin + 1 < z_end) fetch(pa, z_begin + 1);
+  __syncthreads();
+
+  double e_acc = 0.0;
+  // one plane: compute z from LDS buffer cur; fetch z + 2 into fnext; move the
+  // prefetched plane z + 1 (fcur) into the queue and LDS buffer 1 - cur.
+  auto plane_step = [&](int z, int cur, Pf& fcur, Pf& fnext) {
+    if (z + 2 < z_end) fetch(fnext, z + 2);
+    const C* L = lds + cur * PLANE;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int cx = lxk[k] + R, cy = lyk[k] + R;
+      const C c0 = q[k][R];
+      C S{0, 0}, G[3] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+      for (int m = 1; m <= R; ++m) {
+        const C xp = L[(cy * Cfg::kLX + cx + m) * OC + o], xm = L[(cy * Cfg::kLX + cx - m) * OC + o];
+        const C yp = L[((cy + m) * Cfg::kLX + cx) * OC + o], ym = L[((cy - m) * Cfg::kLX + cx) * OC + o];
+        const C zp = q[k][R + m], zm = q[k][R - m];
+        const T al = w.alpha[m - 1], am = w.a1[m - 1];
+        S.re += al * ((xp.re + xm.re) + (yp.re + ym.re) + (zp.re + zm.re));
+        S.im += al * ((xp.im + xm.im) + (yp.im + ym.im) + (zp.im + zm.im));
+        G[0].re += am * (xp.re - xm.re); G[0].im += am * (xp.im - xm.im);
+        G[1].re += am * (yp.re - ym.re); G[1].im += am * (yp.im - ym.im);
+        G[2].re += am * (zp.re - zm.re); G[2].im += am * (zp.im - zm.im);
+      }
+      const T cv = w.centre + vcur[k];
+      C acc{S.re + cv * c0.re + (w.A[0] * G[0].im + w.A[1] * G[1].im + w.A[2] * G[2].im),
+            S.im + cv * c0.im - (w.A[0] * G[0].re + w.A[1] * G[1].re + w.A[2] * G[2].re)};
+      if (args.want_density) {
+        T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
+                   fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+        const int x = x0 + lxk[k], y = y0 + lyk[k];
+        if (o == 0 && x < nx && y < ny) {
+          const long long g = (long long)z * plane + gcol[k];
+          T* dp = (T*)D.dpart + ((long long)chunk * D.n_grid + g) * 4;
+          dp[0] = dv[0]; dp[1] = dv[1]; dp[2] = dv[2]; dp[3] = dv[3];
+        }
+      }
+      if (ok[k]) {
+        if (args.want_energy) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
+        if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
+        C r{cre * acc.re - cim * acc.im, cre * acc.im + cim * acc.re};
+        r.re += bcur[k].re;
+        r.im += bcur[k].im;
+        out[((long long)z * plane + gcol[k]) * no + n] = r;
+      }
+    }
+    if (z + 1 < z_end) {
+      C* Ln = lds + (1 - cur) * PLANE;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+#pragma unroll
+        for (int s = 0; s < KQ - 1; ++s) q[k][s] = q[k][s + 1];
+        q[k][KQ - 1] = fcur.qh[k];
+        bcur[k] = fcur.b[k];
+        vcur[k] = fcur.v[k];
+        Ln[((lyk[k] + R) * Cfg::kLX + (lxk[k] + R)) * OC + o] = q[k][R];
+      }
+#pragma unroll
+      for (int k = 0; k < KH; ++k)
+        if (hl[k] >= 0) Ln[hl[k]] = fcur.h[k];
+    }
+    __syncthreads();
+  };
+  for (int z = z_begin; z < z_end; z += 2) {
+    plane_step(z, 0, pa, pb);
+    if (z + 1 < z_end) plane_step(z + 1, 1, pb, pa);
+  }
+  if (args.want_energy) {
+    const double s = block_sum<double, NT / kWave>(e_acc, red);
+    if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+  }
+}
+
 // rho[g] = sum_chunks dpart[c][g][0];  j[g][d] = sum_chunks dpart[c][g][1 + d] + A_d rho.
 // Items: (dom, block of 256 grid points).  step: A sample; obs: output row.
 template <typename T>
