@@ -73,6 +73,7 @@ enum dcmesh_precision {
 #define DCMESH_FLAG_CHECK_FINITE 0x1u  /* synchronise after the call and test psi for NaN/Inf */
 #define DCMESH_FLAG_PROFILE 0x2u       /* bracket every kernel launch with HIP events on the
                                           call's stream; read with dcmesh_profile_collect */
+#define DCMESH_FLAG_EQ2 0x4u           /* dcmesh_workspace_bytes: size for dcmesh_step_eq2 */
 
 /* Kernel families reported by dcmesh_profile_collect. */
 enum dcmesh_family {
@@ -146,6 +147,21 @@ int dcmesh_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
                 const double* a_dev, int32_t a_per_domain, int64_t a_stride,
                 double dt, int32_t n_steps, const dcmesh_obs* obs,
                 void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* Eq. 2 with the nonlocal operator of Eq. 5: every step applies
+ *     N T4(-i dt h_loc(A_k)) N,   N psi = (psi - delta Psi0 h^3 Psi0^H psi) / |.|,
+ *     delta = i dt v_nl / 2,
+ * i.e. normalised half-steps of the reference-orbital projector v_nl
+ * |Psi0><Psi0| (Eq. 5's Psi(t) -= delta Psi(0) Psi^H(0) Psi(t), each orbital
+ * rescaled to unit norm) around the fourth-order Taylor propagator of the local
+ * Hamiltonian.  The domains' proj and d are ignored.  psi0: host array [n_dom]
+ * of device pointers, [N_g][n_orb] complex, the reference orbitals.  FP64 and
+ * FP32 only.  Workspace: dcmesh_workspace_bytes with DCMESH_FLAG_EQ2. */
+int dcmesh_step_eq2(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                    const void* const* psi0, double v_nl,
+                    const double* a_dev, int32_t a_per_domain, int64_t a_stride,
+                    double dt, int32_t n_steps,
+                    void* work, size_t work_bytes, uint32_t flags, void* stream);
 
 /* Observables of the current orbitals for the field a_dev ([n_a][3], float64,
  * device).  out: host array [n_dom]. */

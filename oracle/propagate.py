@@ -40,3 +40,35 @@ def propagate(dom, a_mid, dt, psi, n_steps=None, want_rho=False, want_j=False,
             obs["energy"].append(O.energy(dom, A, psi))
         psi = taylor4_step(dom, A, dt, psi)
     return psi, {k: np.array(v) for k, v in obs.items() if v}
+
+
+def nonlocal_half_step(dom, psi, psi0, delta):
+    """Eq. 2's nonlocal factor with the nonlocal operator in the space of the
+    reference orbitals (Eq. 5): psi <- psi - delta Psi0 (h^3 Psi0^H psi), then each
+    orbital rescaled to unit norm (the normaliser of Eq. 2)."""
+    p = dom.h ** 3 * (psi.conj().T @ psi0).conj().T        # h^3 Psi0^H psi
+    out = psi - delta * (psi0 @ p)
+    norms = np.sqrt(dom.h ** 3 * np.sum(np.abs(out) ** 2, axis=0))
+    return out / norms[None, :]
+
+
+def eq2_step(dom, A, dt, psi, psi0, v_nl):
+    """One step of Eq. 2: N exp(-i dt h_loc(A)) N with N the normalised
+    half-step 1 - i dt v_nl / 2 of the reference-orbital projector v_nl
+    |Psi0><Psi0| (delta = i dt v_nl / 2 in Eq. 5), and the local propagator
+    taken as the fourth-order Taylor series of h_loc alone."""
+    from synth import Domain
+    loc = Domain(dom.shape, dom.h, dom.fd_order, dom.psi, dom.v_loc,
+                 np.zeros((dom.n_grid, 0), np.complex128), np.zeros(0), dom.occ)
+    delta = 0.5j * dt * v_nl
+    psi = nonlocal_half_step(dom, psi, psi0, delta)
+    psi = taylor4_step(loc, A, dt, psi)
+    return nonlocal_half_step(dom, psi, psi0, delta)
+
+
+def eq2_propagate(dom, a_mid, dt, psi, psi0, v_nl, n_steps=None):
+    a_mid = np.asarray(a_mid, dtype=np.float64)
+    n_steps = len(a_mid) if n_steps is None else n_steps
+    for k in range(n_steps):
+        psi = eq2_step(dom, a_mid[k], dt, psi, psi0, v_nl)
+    return psi

@@ -14,6 +14,7 @@ from .api import (  # noqa: F401
     real_dtype,
     set_tuning,
     step,
+    step_eq2,
     tuning_options,
     workspace_bytes,
 )

@@ -20,11 +20,12 @@ DCMESH_ERR_NONFINITE = 5
 PRECISION = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_fp16": 3}
 FLAG_CHECK_FINITE = 0x1
 FLAG_PROFILE = 0x2
+FLAG_EQ2 = 0x4
 FAMILIES = ("stencil", "project", "reduce", "correct", "density", "energy", "adjoint", "overlap", "split")
 KERNEL = {"stencil": 0, "project": 1, "correct": 2, "zseg": 3}
 
 EXPORTS = (
-    "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_density", "dcmesh_adjoint_step",
+    "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_step_eq2", "dcmesh_density", "dcmesh_adjoint_step",
     "dcmesh_graph_create", "dcmesh_graph_launch", "dcmesh_graph_destroy",
     "dcmesh_set_tuning", "dcmesh_tuning_options", "dcmesh_profile_collect", "dcmesh_last_error",
 )
@@ -66,6 +67,7 @@ def _load():
         "dcmesh_workspace_bytes": [dom_p, I32, I32, U32, ctypes.POINTER(SZ)],
         "dcmesh_step": [dom_p, I32, I32, P, I32, I64, D, I32, ctypes.POINTER(DcmeshObs), P, SZ, U32, P],
         "dcmesh_density": [dom_p, I32, I32, P, I32, ctypes.POINTER(DcmeshDensityOut), P, SZ, U32, P],
+        "dcmesh_step_eq2": [dom_p, I32, I32, ctypes.POINTER(P), D, P, I32, I64, D, I32, P, SZ, U32, P],
         "dcmesh_adjoint_step": [dom_p, I32, I32, ctypes.POINTER(P), P, I32, D, P, P, SZ, U32, P],
         "dcmesh_graph_create": [dom_p, I32, I32, P, I32, I64, D, I32, ctypes.POINTER(DcmeshObs), P, SZ, U32, P,
                                 ctypes.POINTER(P)],

@@ -94,10 +94,11 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def workspace_bytes(domains: Sequence[Domain], precision: str) -> int:
+def workspace_bytes(domains: Sequence[Domain], precision: str, eq2: bool = False) -> int:
     arr = _doms(domains, precision)
     out = ctypes.c_size_t(0)
-    check(lib.dcmesh_workspace_bytes(arr, len(domains), PRECISION[precision], 0, ctypes.byref(out)))
+    flags = _lib.FLAG_EQ2 if eq2 else 0
+    check(lib.dcmesh_workspace_bytes(arr, len(domains), PRECISION[precision], flags, ctypes.byref(out)))
     return out.value
 
 
@@ -111,8 +112,8 @@ class Workspace:
         self.nbytes = nbytes
 
     @classmethod
-    def for_domains(cls, domains, precision):
-        return cls(workspace_bytes(domains, precision), domains[0].psi.device)
+    def for_domains(cls, domains, precision, eq2=False):
+        return cls(workspace_bytes(domains, precision, eq2), domains[0].psi.device)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -137,6 +138,20 @@ def step(domains: Sequence[Domain], a: torch.Tensor, dt: float, n_steps: int, pr
     flags = (_lib.FLAG_CHECK_FINITE if check_finite else 0) | (_lib.FLAG_PROFILE if profile else 0)
     check(lib.dcmesh_step(arr, len(domains), PRECISION[precision], a.data_ptr(), int(a_per_domain), stride,
                           float(dt), int(n_steps), o, work.ptr, work.nbytes, flags, _stream(stream)))
+
+
+def step_eq2(domains: Sequence[Domain], psi0: Sequence[torch.Tensor], v_nl: float, a: torch.Tensor, dt: float,
+             n_steps: int, precision: str, work: Workspace, a_per_domain: bool = False, stream=None):
+    """Eq. 2 steps with the reference-orbital nonlocal operator of Eq. 5 (see
+    dcmesh_step_eq2); psi0: per-domain reference orbitals like psi."""
+    arr = _doms(domains, precision)
+    for p0, d in zip(psi0, domains):
+        if p0.dtype != d.psi.dtype or tuple(p0.shape) != tuple(d.psi.shape) or not p0.is_contiguous():
+            raise ValueError("psi0 must match psi in dtype, shape and be contiguous")
+    pp = (ctypes.c_void_p * len(psi0))(*[p.data_ptr() for p in psi0])
+    check(lib.dcmesh_step_eq2(arr, len(domains), PRECISION[precision], pp, float(v_nl), a.data_ptr(),
+                              int(a_per_domain), a.shape[-2], float(dt), int(n_steps), work.ptr, work.nbytes, 0,
+                              _stream(stream)))
 
 
 def density(domains: Sequence[Domain], a: torch.Tensor, precision: str, work: Workspace,

@@ -55,6 +55,10 @@ struct DomDesc {
   int item0_reduce;             // ... in its reduce launch
   int item0_elem;               // ... in its elementwise launch
   int n_chunks;                 // orbital chunks of the stencil sweep
+  int item0_rows;               // first item of this domain in its row-block launch
+  int n_rows_blocks;            // row blocks (256 grid points) of the domain
+  double* cn_part;              // [n_rows_blocks][n_orb] column-norm partials
+  double* cn_inv;               // [n_orb] inverse column norms
   void* dpart;                  // [n_chunks][N_g][4] density / current partials
   // per-step observables (may be null)
   void* rho;                    // [.][N_g]

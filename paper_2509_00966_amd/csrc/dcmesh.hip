@@ -169,6 +169,7 @@ struct Plan {
   std::vector<Launch> stencil, proj, reduce, corr, dens, elem, energy, ovl_proj, ovl_reduce;
   std::vector<Launch> presplit, absmax_b, absmax_u, splitq;   // split-precision modes
   std::vector<Launch> dfinish;                                 // density partials -> rho, j
+  std::vector<Launch> rows;                                    // 256-point row blocks (column norms)
   size_t bytes_tables = 0, bytes_total = 0;
   size_t off_items = 0, off_flag = 0;
   bool any_proj = false;
@@ -323,6 +324,13 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
   group_launch(P.dfinish, P.items, n_dom, [](int) { return 0; }, [&](int i, std::vector<Item>& it) {
     for (long long b = 0; b < cdiv(P.desc[i].n_grid, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
   });
+  group_launch(P.rows, P.items, n_dom, [](int) { return 0; },
+               [&](int i, std::vector<Item>& it) {
+                 DomDesc& D = P.desc[i];
+                 D.n_rows_blocks = (int)cdiv(D.n_grid, kBlock);
+                 for (int b = 0; b < D.n_rows_blocks; ++b) it.push_back({i, b, 0, 0});
+               },
+               [&](int i, int first) { P.desc[i].item0_rows = first; });
   group_launch(P.energy, P.items, n_dom, [](int) { return 0; },
                [&](int i, std::vector<Item>& it) { it.push_back({i, 0, 0, 0}); });
   // overlap S = h^3 Psi^H Psi (always FP64 arithmetic)
@@ -406,6 +414,8 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     // sized for the smallest orbital chunk of any stencil variant, so the
     // workspace does not depend on the tile choice
     D.dpart = take((size_t)cdiv(D.n_orb, 4) * D.n_grid * 4 * rs);
+    D.cn_part = (double*)take(sizeof(double) * (size_t)D.n_rows_blocks * D.n_orb);
+    D.cn_inv = (double*)take(sizeof(double) * D.n_orb);
     if (is_split(prec) && D.n_proj > 0) {
       const size_t nbs = (size_t)D.n_grid * D.ldbs * 2, nbt = (size_t)D.n_proj * D.ldbt * 2;   // 16-bit values
       D.bs_hi = take(nbs); D.bs_lo = take(nbs);
@@ -641,9 +651,9 @@ void launch_project(const Ctx& c, int u_slot) {
 }
 
 template <typename T>
-void launch_reduce(const Ctx& c, double cre, double cim, int occ_scale, int want_energy) {
+void launch_reduce(const Ctx& c, double cre, double cim, int occ_scale, int want_energy, int unit_d = 0) {
   ProfScope prof_(DCMESH_FAM_REDUCE, c.s);
-  ReduceArgs a{cre, cim, occ_scale, want_energy, 0, c.P->prec == DCMESH_SPLIT_FP16 ? 1 : 0};
+  ReduceArgs a{cre, cim, occ_scale, want_energy, 0, c.P->prec == DCMESH_SPLIT_FP16 ? 1 : 0, unit_d};
   for (const Launch& L : c.P->reduce)
     k_reduce<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
 }
@@ -743,9 +753,10 @@ void launch_correct_split(const Ctx& c, int out_slot) {
 // projector correction added in place).
 template <typename T>
 void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double cre, double cim,
-                 int occ_scale, int step, int want_energy, int want_density = 0) {
+                 int occ_scale, int step, int want_energy, int want_density = 0, bool nonlocal = true) {
   const int prec = c.P->prec;
-  if (c.P->any_proj) {
+  const bool nl = nonlocal && c.P->any_proj;
+  if (nl) {
     if (prec == DCMESH_SPLIT_BF16) {
       launch_project_split<0>(c, u_slot);
     } else if (prec == DCMESH_SPLIT_FP16) {
@@ -758,7 +769,7 @@ void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double c
   }
   StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy, want_density};
   launch_stencil<T>(c, sa);
-  if (c.P->any_proj) {
+  if (nl) {
     if (prec == DCMESH_SPLIT_BF16)
       launch_correct_split<0>(c, out_slot);
     else if (prec == DCMESH_SPLIT_FP16)
@@ -806,7 +817,7 @@ void launch_overlap(const Ctx& c) {
   ProjArgs a{SLOT_PSI, SLOT_PSI, 1};
   for (const Launch& L : c.P->ovl_proj)
     k_project<T, double, 64, 64, kProjKG, 2><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
-  ReduceArgs r{1.0, 0.0, 0, 0, 1, 0};
+  ReduceArgs r{1.0, 0.0, 0, 0, 1, 0, 0};
   for (const Launch& L : c.P->ovl_reduce) k_reduce<double><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, r);
 }
 
@@ -836,6 +847,38 @@ int prepare(CallSetup& cs, const dcmesh_domain* doms, int32_t n_dom, int32_t pre
   rc = stage_tables(P, (char*)work, s, cap != hipStreamCaptureStatusNone, &cs.keep);
   if (rc) return rc;
   cs.c = Ctx{&P, (const DomDesc*)work, (const Item*)((char*)work + P.off_items), s};
+  return DCMESH_OK;
+}
+
+// psi <- psi / |psi_n| column by column (fixed-order FP64 norms).
+template <typename T>
+void launch_normalise(const Ctx& c) {
+  ProfScope prof_(DCMESH_FAM_REDUCE, c.s);
+  for (const Launch& L : c.P->rows) k_colnorm_partial<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+  for (const Launch& L : c.P->energy) k_colnorm_final<<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+  for (const Launch& L : c.P->rows) k_colnorm_scale<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+}
+
+// Eq. 2 with the nonlocal operator of Eq. 5: per step N T4(-i dt h_loc(A_k)) N,
+// N psi = normalise(psi - delta Psi0 h^3 Psi0^H psi), delta = i dt v_nl / 2.
+// The domain descriptors carry Psi0 as their projector array (n_proj = n_orb).
+template <typename T>
+int run_step_eq2(CallSetup& cs, int32_t n_steps, double dt, double v_nl) {
+  const Ctx& c = cs.c;
+  auto half = [&]() {
+    launch_project<T>(c, SLOT_PSI);
+    launch_reduce<T>(c, 0.0, -0.5 * dt * v_nl, 0, 0, 1);     // coef = -delta, D = 1
+    launch_correct<T>(c, SLOT_PSI);
+    launch_normalise<T>(c);
+  };
+  for (int k = 0; k < n_steps; ++k) {
+    half();
+    apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, 0, 0, false);
+    apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, k, 0, 0, false);
+    apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B0, 0.0, -dt / 2, 0, k, 0, 0, false);
+    apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_PSI, 0.0, -dt, 0, k, 0, 0, false);
+    half();
+  }
   return DCMESH_OK;
 }
 
@@ -933,10 +976,19 @@ const char* dcmesh_last_error(void) { return g_err.c_str(); }
 
 int dcmesh_workspace_bytes(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, uint32_t flags,
                            size_t* bytes) {
-  (void)flags;
   if (!bytes) return fail(DCMESH_ERR_INVALID_ARGUMENT, "bytes is NULL");
   int rc = validate_domains(doms, n_dom, precision);
   if (rc) return rc;
+  std::vector<dcmesh_domain> eq2;
+  if (flags & DCMESH_FLAG_EQ2) {     // the reference orbitals take the place of the projectors
+    eq2.assign(doms, doms + n_dom);
+    for (auto& d : eq2) {
+      d.n_proj = d.n_orb;
+      d.proj = d.psi;
+      d.d = d.occ;
+    }
+    doms = eq2.data();
+  }
   Plan P;
   build_plan(P, doms, n_dom, precision, nullptr);
   *bytes = P.bytes_total;
@@ -949,6 +1001,48 @@ int dcmesh_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, con
   CallSetup cs;
   return step_impl(doms, n_dom, precision, a_dev, a_per_domain, a_stride, dt, n_steps, obs, work, work_bytes,
                    flags, (hipStream_t)stream, cs);
+}
+
+int dcmesh_step_eq2(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const void* const* psi0,
+                    double v_nl, const double* a_dev, int32_t a_per_domain, int64_t a_stride, double dt,
+                    int32_t n_steps, void* work, size_t work_bytes, uint32_t flags, void* stream) {
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  if (precision != DCMESH_FP64 && precision != DCMESH_FP32)
+    return fail(DCMESH_ERR_UNSUPPORTED, "dcmesh_step_eq2 runs in FP64 or FP32");
+  if (!psi0) return fail(DCMESH_ERR_INVALID_ARGUMENT, "psi0 is NULL");
+  for (int i = 0; i < n_dom; ++i)
+    if (!psi0[i]) return fail(DCMESH_ERR_INVALID_ARGUMENT, "psi0[" + std::to_string(i) + "] is NULL");
+  if (n_steps < 0) return fail(DCMESH_ERR_INVALID_ARGUMENT, "n_steps must be >= 0");
+  if (n_steps > 0 && !a_dev) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_dev is NULL");
+  if (a_stride < n_steps) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_stride must be >= n_steps");
+  if (!std::isfinite(dt) || !std::isfinite(v_nl)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "dt and v_nl must be finite");
+  std::vector<dcmesh_domain> eq2(doms, doms + n_dom);
+  for (int i = 0; i < n_dom; ++i) {
+    eq2[i].n_proj = eq2[i].n_orb;
+    eq2[i].proj = psi0[i];
+    eq2[i].d = eq2[i].occ;      // not read: the reduce runs with D = 1
+  }
+  CallSetup cs;
+  hipStream_t s = (hipStream_t)stream;
+  rc = prepare(cs, eq2.data(), n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
+    for (int i = 0; i < n_dom; ++i) {
+      DomDesc& D = P.desc[i];
+      D.slot[SLOT_PSI] = eq2[i].psi;
+      D.v = eq2[i].v_loc;
+      D.proj = eq2[i].proj;
+      D.d = eq2[i].d;
+      D.occ = eq2[i].occ;
+      D.a = a_dev + (a_per_domain ? (long long)i * a_stride * 3 : 0);
+    }
+  });
+  if (rc) return rc;
+  if (precision == DCMESH_FP64)
+    rc = run_step_eq2<double>(cs, n_steps, dt, v_nl);
+  else
+    rc = run_step_eq2<float>(cs, n_steps, dt, v_nl);
+  if (rc) return rc;
+  return finish(cs, flags);
 }
 
 int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const double* a_dev,

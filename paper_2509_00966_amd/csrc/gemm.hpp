@@ -189,6 +189,7 @@ struct ReduceArgs {
   int want_energy;     // nonlocal energy partials sum f D |P|^2
   int write_overlap;   // overlap mode: write h^3 * sum to D.overlap (complex128)
   int want_qmax;       // gather max |Q'| into D.maxbits[2] (FP16 split scaling)
+  int unit_d;          // D = 1 (the reference-orbital projector of Eq. 5)
 };
 
 // Items: (dom, block index over n_proj * n_orb pairs).  Deterministic: the
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
       TC* P = (TC*)D.pmat;
       P[(long long)p * no2 + 2 * n] = pr;
       P[(long long)p * no2 + 2 * n + 1] = pi;
-      const TC dp = ((const TC*)D.d)[p];
+      const TC dp = args.unit_d ? (TC)1 : ((const TC*)D.d)[p];
       const TC fn = ((const TC*)D.occ)[n];
       const TC sc = args.occ_scale ? dp * fn : dp;
       const TC qr = sc * ((TC)args.cre * pr - (TC)args.cim * pi);

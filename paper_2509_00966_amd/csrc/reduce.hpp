@@ -195,3 +195,58 @@ __global__ __launch_bounds__(kBlock) void k_nonfinite(const DomDesc* __restrict_
 __global__ void k_fill_int(int* p, int v) { *p = v; }
 
 }  // namespace dcm
+
+namespace dcm {
+
+// Column norms of the psi slot: partial sums of |psi[g][n]|^2 over 256 grid
+// rows per block, one FP64 value per (block, orbital).  Items: (dom, row block).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_colnorm_partial(const DomDesc* __restrict__ doms,
+                                                            const Item* __restrict__ items) {
+  using C = Cplx<T>;
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int no = D.n_orb;
+  const long long g0 = (long long)it.a * kBlock, g1 = min(g0 + kBlock, D.n_grid);
+  const C* __restrict__ psi = (const C*)D.slot[SLOT_PSI];
+  for (int n = threadIdx.x; n < no; n += kBlock) {
+    double s = 0;
+    for (long long g = g0; g < g1; ++g) {
+      const C c = psi[g * no + n];
+      s += (double)c.re * c.re + (double)c.im * c.im;
+    }
+    D.cn_part[(long long)(blockIdx.x - D.item0_rows) * no + n] = s;
+  }
+}
+
+// inv[n] = 1 / sqrt(h^3 sum_blocks partial[blk][n]) in block order.  Items: one per domain.
+__global__ __launch_bounds__(kBlock) void k_colnorm_final(const DomDesc* __restrict__ doms,
+                                                          const Item* __restrict__ items) {
+  const DomDesc& D = doms[items[blockIdx.x].dom];
+  const int no = D.n_orb;
+  const double h3 = D.h * D.h * D.h;
+  for (int n = threadIdx.x; n < no; n += kBlock) {
+    double s = 0;
+    for (int b = 0; b < D.n_rows_blocks; ++b) s += D.cn_part[(long long)b * no + n];
+    D.cn_inv[n] = 1.0 / sqrt(h3 * s);
+  }
+}
+
+// psi[g][n] *= inv[n].  Items: (dom, row block).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_colnorm_scale(const DomDesc* __restrict__ doms,
+                                                          const Item* __restrict__ items) {
+  using C = Cplx<T>;
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int no = D.n_orb;
+  const long long g0 = (long long)it.a * kBlock, g1 = min(g0 + kBlock, D.n_grid);
+  C* __restrict__ psi = (C*)D.slot[SLOT_PSI];
+  for (long long e = g0 * no + threadIdx.x; e < g1 * no; e += kBlock) {
+    const T s = (T)D.cn_inv[e % no];
+    psi[e].re *= s;
+    psi[e].im *= s;
+  }
+}
+
+}  // namespace dcm
