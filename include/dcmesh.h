@@ -129,8 +129,8 @@ typedef struct dcmesh_density_out {
   double* overlap;
 } dcmesh_density_out;
 
-/* Workspace needed by dcmesh_step, dcmesh_density and dcmesh_adjoint_step for
- * these domains and precision (one size serves all three).  Host-only; writes
+/* Workspace needed by dcmesh_step, dcmesh_density, dcmesh_occupations and
+ * dcmesh_adjoint_step for these domains and precision (one size serves all).  Host-only; writes
  * *bytes.  Workspace pointers must be 256-byte aligned. */
 int dcmesh_workspace_bytes(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
                            uint32_t flags, size_t* bytes);
@@ -169,6 +169,27 @@ int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
                    const double* a_dev, int32_t a_per_domain,
                    const dcmesh_density_out* out,
                    void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* Occupations of the reference orbitals and the number of excited electrons,
+ * the quantities the local field dynamics hands to the atomic dynamics
+ * (Sec. V.A.3 and V.A.8).  With the reference orbitals psi0 (Eq. 5's Psi(0)):
+ *     S_sn  = h^3 <psi0_s | psi_n>                          (FP64 accumulation)
+ *     f_s   = sum_n f_n |S_sn|^2
+ *     n_exc = sum_n f_n (h^3 <psi_n|psi_n> - sum_s |S_sn|^2)
+ * n_exc is the occupation-weighted norm of the orbitals outside the span of
+ * orthonormal reference orbitals (the paper gives the quantities, not the
+ * formula; this is the projection form).
+ *   psi0     host array [n_dom] of device pointers, [N_g][n_orb] complex in the
+ *            precision's storage type (as psi); read only
+ *   overlap  NULL, or host array [n_dom] whose non-NULL entries receive S,
+ *            device [n_orb][n_orb] complex128 (row s, column n)
+ *   f_out    host array [n_dom] of device float64 [n_orb] outputs
+ *   n_exc    device float64 [n_dom] output
+ * Deterministic (fixed summation orders).  Workspace as dcmesh_step. */
+int dcmesh_occupations(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                       const void* const* psi0, double* const* overlap,
+                       double* const* f_out, double* n_exc,
+                       void* work, size_t work_bytes, uint32_t flags, void* stream);
 
 /* One step of the adjoint recursion for the gradient of a loss L(psi_N):
  *     lambda_k = U_k^H lambda_{k+1} = T4(+i dt H(A_k)) lambda_{k+1}

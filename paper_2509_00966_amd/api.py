@@ -167,6 +167,36 @@ def density(domains: Sequence[Domain], a: torch.Tensor, precision: str, work: Wo
                              work.ptr, work.nbytes, 0, _stream(stream)))
 
 
+def occupations(domains: Sequence[Domain], psi0: Sequence[torch.Tensor], precision: str, work: Workspace,
+                overlap: Optional[Sequence[Optional[torch.Tensor]]] = None, stream=None):
+    """Occupations f_s of the reference orbitals psi0 and the excited-electron
+    count n_exc of every domain.  Returns (list of float64 [N_o] tensors,
+    float64 [n_dom] tensor).  ``overlap``: optional per-domain float64
+    [N_o, N_o, 2] outputs for S = h^3 Psi0^H Psi."""
+    arr = _doms(domains, precision)
+    cd = _CPLX[precision]
+    for p0, d in zip(psi0, domains):
+        if p0.dtype != cd or tuple(p0.shape) != tuple(d.psi.shape) or not p0.is_contiguous():
+            raise ValueError("psi0 must match psi in dtype, shape and be contiguous")
+    if len(psi0) != len(domains):
+        raise ValueError("one psi0 per domain")
+    dev = domains[0].psi.device
+    f = [torch.empty(d.psi.shape[1], dtype=torch.float64, device=dev) for d in domains]
+    n_exc = torch.empty(len(domains), dtype=torch.float64, device=dev)
+    pp = (ctypes.c_void_p * len(domains))(*[x.data_ptr() for x in psi0])
+    fp = (ctypes.c_void_p * len(domains))(*[x.data_ptr() for x in f])
+    op = None
+    if overlap is not None:
+        for o, d in zip(overlap, domains):
+            n = d.psi.shape[1]
+            if o is not None and (o.dtype != torch.float64 or tuple(o.shape) != (n, n, 2) or not o.is_contiguous()):
+                raise ValueError("overlap outputs are contiguous float64 [N_o, N_o, 2]")
+        op = (ctypes.c_void_p * len(domains))(*[_ptr(o) for o in overlap])
+    check(lib.dcmesh_occupations(arr, len(domains), PRECISION[precision], pp, op, fp, n_exc.data_ptr(),
+                                 work.ptr, work.nbytes, 0, _stream(stream)))
+    return f, n_exc
+
+
 def adjoint_step(domains: Sequence[Domain], lambdas: Sequence[torch.Tensor], a: torch.Tensor, dt: float,
                  grad: torch.Tensor, precision: str, work: Workspace, a_per_domain: bool = False, stream=None):
     """lambda <- U^H lambda in place; grad (float64 device, [3] or [n_dom, 3]) += dL/dA."""

@@ -66,6 +66,10 @@ struct DomDesc {
   double* energy;               // [.]
   double* grad;                 // [3] gradient accumulator (adjoint)
   double* overlap;              // [n_orb][n_orb] complex128
+  double* smat;                 // workspace [n_orb][n_orb] complex128 (cross overlap)
+  double* f_occ;                // [n_orb] occupations of the reference orbitals
+  double* n_exc;                // one value: electrons outside the reference span
+  int item0_occ;                // first item of this domain in its occupation-row launch
   // split-precision operands (16-bit hi and lo planes), null otherwise
   void* bs_hi; void* bs_lo;     // [N_g][ldbs]       projectors as stored
   void* bt_hi; void* bt_lo;     // [n_proj][ldbt]    projectors transposed

@@ -170,6 +170,7 @@ struct Plan {
   std::vector<Launch> presplit, absmax_b, absmax_u, splitq;   // split-precision modes
   std::vector<Launch> dfinish;                                 // density partials -> rho, j
   std::vector<Launch> rows;                                    // 256-point row blocks (column norms)
+  std::vector<Launch> occ_rows;                                // 4 reference orbitals per block
   size_t bytes_tables = 0, bytes_total = 0;
   size_t off_items = 0, off_flag = 0;
   bool any_proj = false;
@@ -344,6 +345,11 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     const DomDesc& D = P.desc[i];
     for (long long b = 0; b < cdiv((long long)D.n_orb * D.n_orb, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
   });
+  group_launch(P.occ_rows, P.items, n_dom, [](int) { return 0; },
+               [&](int i, std::vector<Item>& it) {
+                 for (int b = 0; b < cdiv(P.desc[i].n_orb, kBlock / kWave); ++b) it.push_back({i, b, 0, 0});
+               },
+               [&](int i, int first) { P.desc[i].item0_occ = first; });
 
   if (is_split(prec)) {
     auto has_p = [&](int i) { return doms[i].n_proj > 0 ? 0 : -1; };
@@ -416,6 +422,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.dpart = take((size_t)cdiv(D.n_orb, 4) * D.n_grid * 4 * rs);
     D.cn_part = (double*)take(sizeof(double) * (size_t)D.n_rows_blocks * D.n_orb);
     D.cn_inv = (double*)take(sizeof(double) * D.n_orb);
+    D.smat = (double*)take(16 * (size_t)D.n_orb * D.n_orb);
     if (is_split(prec) && D.n_proj > 0) {
       const size_t nbs = (size_t)D.n_grid * D.ldbs * 2, nbt = (size_t)D.n_proj * D.ldbt * 2;   // 16-bit values
       D.bs_hi = take(nbs); D.bs_lo = take(nbs);
@@ -811,14 +818,27 @@ void launch_grad(const Ctx& c, int mu_slot, int u_slot, double cre, double cim) 
     k_grad_partial<T, kEPT><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, mu_slot, u_slot, cre, cim);
 }
 
+// S = h^3 A^H Psi into D.overlap, FP64 accumulation, for A the psi-sized
+// buffer in a_slot (Psi itself for the orbital overlap).
 template <typename T>
-void launch_overlap(const Ctx& c) {
+void launch_overlap(const Ctx& c, int a_slot = SLOT_PSI) {
   ProfScope prof_(DCMESH_FAM_OVERLAP, c.s);
-  ProjArgs a{SLOT_PSI, SLOT_PSI, 1};
+  ProjArgs a{a_slot, SLOT_PSI, 1};
   for (const Launch& L : c.P->ovl_proj)
     k_project<T, double, 64, 64, kProjKG, 2><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, a);
   ReduceArgs r{1.0, 0.0, 0, 0, 1, 0, 0};
   for (const Launch& L : c.P->ovl_reduce) k_reduce<double><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, r);
+}
+
+// f_s and n_exc from the cross overlap with the reference orbitals in
+// SLOT_LAMBDA.
+template <typename T>
+void launch_occupations(const Ctx& c) {
+  launch_overlap<T>(c, SLOT_LAMBDA);
+  ProfScope prof_(DCMESH_FAM_OVERLAP, c.s);
+  for (const Launch& L : c.P->rows) k_colnorm_partial<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+  for (const Launch& L : c.P->occ_rows) k_occ_rows<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
+  for (const Launch& L : c.P->energy) k_occ_final<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
 }
 
 // ---------------------------------------------------------------------------
@@ -1091,6 +1111,33 @@ int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, 
     }
   }
   if (ovl) f64 ? launch_overlap<double>(cs.c) : launch_overlap<float>(cs.c);
+  return finish(cs, flags);
+}
+
+int dcmesh_occupations(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const void* const* psi0,
+                       double* const* overlap, double* const* f_out, double* n_exc, void* work,
+                       size_t work_bytes, uint32_t flags, void* stream) {
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  if (!psi0 || !f_out || !n_exc) return fail(DCMESH_ERR_INVALID_ARGUMENT, "psi0, f_out and n_exc are required");
+  for (int i = 0; i < n_dom; ++i)
+    if (!psi0[i] || !f_out[i])
+      return fail(DCMESH_ERR_INVALID_ARGUMENT, "psi0[" + std::to_string(i) + "] or f_out[" + std::to_string(i) + "] is NULL");
+  CallSetup cs;
+  hipStream_t s = (hipStream_t)stream;
+  rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
+    for (int i = 0; i < n_dom; ++i) {
+      DomDesc& D = P.desc[i];
+      D.slot[SLOT_PSI] = doms[i].psi;
+      D.slot[SLOT_LAMBDA] = const_cast<void*>(psi0[i]);
+      D.occ = doms[i].occ;
+      D.overlap = overlap && overlap[i] ? overlap[i] : D.smat;
+      D.f_occ = f_out[i];
+      D.n_exc = n_exc + i;
+    }
+  });
+  if (rc) return rc;
+  is_fp64(precision) ? launch_occupations<double>(cs.c) : launch_occupations<float>(cs.c);
   return finish(cs, flags);
 }
 

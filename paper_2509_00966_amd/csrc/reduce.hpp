@@ -249,4 +249,54 @@ __global__ __launch_bounds__(kBlock) void k_colnorm_scale(const DomDesc* __restr
   }
 }
 
+// Occupations of the reference orbitals from the cross overlap
+// S_sn = h^3 <psi0_s|psi_n> (in D.overlap, complex128):
+//     f_s = sum_n f_n |S_sn|^2.
+// One wave per reference orbital s; the lanes take n in a fixed order and the
+// wave sum has a fixed shape.  Items: (dom, block of 4 rows).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_occ_rows(const DomDesc* __restrict__ doms,
+                                                     const Item* __restrict__ items) {
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int no = D.n_orb;
+  const int s = it.a * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (s >= no) return;                 // whole waves leave together
+  const T* __restrict__ occ = (const T*)D.occ;
+  const double* __restrict__ S = D.overlap + (long long)s * no * 2;
+  double acc = 0.0;
+  for (int n = lane; n < no; n += kWave) {
+    const double re = S[2 * n], im = S[2 * n + 1];
+    acc += (double)occ[n] * (re * re + im * im);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) D.f_occ[s] = acc;
+}
+
+// n_exc = sum_n f_n (h^3 |psi_n|^2 - sum_s |S_sn|^2), the occupation-weighted
+// norm outside the reference span.  The column norms come from the
+// k_colnorm_partial block partials, summed in block order.  One block per domain.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_occ_final(const DomDesc* __restrict__ doms,
+                                                      const Item* __restrict__ items) {
+  __shared__ double red[kBlock / kWave];
+  const DomDesc& D = doms[items[blockIdx.x].dom];
+  const int no = D.n_orb;
+  const double h3 = D.h * D.h * D.h;
+  const T* __restrict__ occ = (const T*)D.occ;
+  double t = 0.0;
+  for (int n = threadIdx.x; n < no; n += kBlock) {
+    double nrm = 0.0, col = 0.0;
+    for (int b = 0; b < D.n_rows_blocks; ++b) nrm += D.cn_part[(long long)b * no + n];
+    for (int s = 0; s < no; ++s) {
+      const double re = D.overlap[((long long)s * no + n) * 2], im = D.overlap[((long long)s * no + n) * 2 + 1];
+      col += re * re + im * im;
+    }
+    t += (double)occ[n] * (h3 * nrm - col);
+  }
+  t = block_sum(t, red);
+  if (threadIdx.x == 0) D.n_exc[0] = t;
+}
+
 }  // namespace dcm
