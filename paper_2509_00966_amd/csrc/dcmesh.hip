@@ -374,17 +374,20 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     });
   }
 
-  // Workspace layout.  The item tables get room for the largest item count
-  // any tile variant could produce (smallest tiles: stencil 8 x 4 columns x
-  // 4 orbitals over segments of >= min(nz, 16) planes; projector products in
-  // 32 x 32 tiles), so the workspace size does not depend on the tuning.
+  // Workspace layout.  The item tables and the stencil's energy partials get
+  // room for the largest count any tile variant could produce (smallest
+  // tiles: stencil 8 x 4 columns x 4 orbitals over segments of >= min(nz, 8)
+  // planes; projector products in 32 x 32 tiles), so the workspace size does
+  // not depend on the tuning.
+  auto stencil_bound = [](const DomDesc& D) {
+    return cdiv(D.nx, 8) * cdiv(D.ny, 4) * cdiv(D.n_orb, 4) * cdiv(D.nz, std::min(D.nz, 8));
+  };
   size_t variable = 0, bound = 0;
   for (const auto* fam : {&P.stencil, &P.proj, &P.corr})
     for (const Launch& L : *fam) variable += L.count;
   for (int i = 0; i < n_dom; ++i) {
     const DomDesc& D = P.desc[i];
-    const long long nzs = cdiv(D.nz, std::min(D.nz, 16));
-    bound += (size_t)(cdiv(D.nx, 8) * cdiv(D.ny, 4) * cdiv(D.n_orb, 4) * nzs);
+    bound += (size_t)stencil_bound(D);
     if (D.n_proj > 0) {
       bound += (size_t)(D.n_split * cdiv(D.n_proj, 32) * cdiv(2 * D.n_orb, 32));
       bound += (size_t)(cdiv(D.n_grid, 32) * cdiv(2 * D.n_orb, 32));
@@ -414,7 +417,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.qmat = take(2 * (size_t)D.n_proj * D.ldq * acc);
     // three-product (Gauss) planes of coef D P for the FP32 correction
     D.qmat3 = prec == DCMESH_FP32 ? take(3 * (size_t)D.n_proj * D.ldq3 * sizeof(float)) : nullptr;
-    D.e_loc = (double*)take(sizeof(double) * std::max(1, D.n_e_loc));
+    D.e_loc = (double*)take(sizeof(double) * (size_t)std::max<long long>(D.n_e_loc, stencil_bound(D)));
     D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
     D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
     // sized for the smallest orbital chunk of any stencil variant, so the

@@ -114,3 +114,37 @@ def test_workspace_grows_with_problem():
     assert out2.value > out1.value
     assert L.lib.dcmesh_workspace_bytes(_dom(L), 1, 0, 0, ctypes.byref(out2)) == 0   # FP64 is bigger
     assert out2.value > out1.value
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_workspace_size_does_not_depend_on_tuning(precision):
+    """Every tile variant and z-segment choice fits the one workspace size
+    (regression: the stencil's energy partials once followed the variant)."""
+    L = _lib()
+    shapes = [(20, 31, 40, 16, 32), (37, 22, 29, 70, 136), (64, 64, 64, 128, 512), (9, 10, 11, 5, 0)]
+    doms = (L.DcmeshDomain * len(shapes))(*[
+        L.DcmeshDomain(nx=a, ny=b, nz=c, fd_order=6, n_orb=o, n_proj=p, h=0.4, psi=0x10000,
+                       v_loc=0x10000, proj=0x10000 if p else None, d=0x10000 if p else None,
+                       occ=0x10000) for a, b, c, o, p in shapes])
+
+    def size():
+        out = ctypes.c_size_t(0)
+        assert L.lib.dcmesh_workspace_bytes(doms, len(shapes), precision, 0, ctypes.byref(out)) == 0
+        return out.value
+
+    n = ctypes.c_int32(0)
+    try:
+        base = size()
+        for k in range(4):
+            assert L.lib.dcmesh_tuning_options(k, ctypes.byref(n)) == 0
+            for v in range(n.value):
+                assert L.lib.dcmesh_set_tuning(k, v) == 0
+                assert size() == base, (k, v)
+            assert L.lib.dcmesh_set_tuning(k, -1) == 0
+        # every family at its smallest tiles at once
+        for k, v in ((0, 3), (1, 1), (2, 2), (3, 1)):
+            assert L.lib.dcmesh_set_tuning(k, v) == 0
+        assert size() == base
+    finally:
+        for k in range(4):
+            L.lib.dcmesh_set_tuning(k, -1)
