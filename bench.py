@@ -72,8 +72,9 @@ def main():
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the step has no cross-GPU part in this build "
-              "(domains are independent; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: domains are independent, so a run over several GPUs "
+              "would place whole domains (or orbital bands) on each and has no cross-GPU part to time.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -10,6 +10,7 @@ from .api import (  # noqa: F401
     adjoint_step,
     complex_dtype,
     density,
+    occupations,
     profile_collect,
     real_dtype,
     set_tuning,

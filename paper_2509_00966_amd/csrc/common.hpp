@@ -23,6 +23,23 @@ enum Slot : int {
   N_SLOTS = 8
 };
 
+// Every pointer a kernel reaches through a domain descriptor addresses device
+// memory.  The device pass declares the descriptor's pointer fields in the
+// global address space, so that the compiler emits global (not flat) loads and
+// stores for everything derived from them: a flat access also counts against
+// the LDS wait counter, which would make each LDS wait in a kernel wait for its
+// outstanding prefetches too.  The host pass sees the same layout with plain
+// pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DCM_GLOBAL __attribute__((address_space(1)))
+#else
+#define DCM_GLOBAL
+#endif
+
+// Host code stores device addresses into descriptor fields through this cast.
+template <typename T>
+__host__ __device__ inline DCM_GLOBAL T* as_global(T* p) { return (DCM_GLOBAL T*)p; }
+
 // One domain as the kernels see it.  Built on the host, copied into the head
 // of the workspace once per call.
 struct DomDesc {
@@ -30,23 +47,23 @@ struct DomDesc {
   int n_orb, n_proj;
   long long n_grid;
   double h;
-  void* slot[N_SLOTS];          // psi-sized complex buffers
-  const void* v;                // [N_g] real
-  const void* proj;             // [N_g][n_proj] complex
-  const void* d;                // [n_proj] real
-  const void* occ;              // [n_orb] real
-  const double* a;              // A samples of this domain, [.][3]
+  DCM_GLOBAL void* slot[N_SLOTS];          // psi-sized complex buffers
+  const DCM_GLOBAL void* v;                // [N_g] real
+  const DCM_GLOBAL void* proj;             // [N_g][n_proj] complex
+  const DCM_GLOBAL void* d;                // [n_proj] real
+  const DCM_GLOBAL void* occ;              // [n_orb] real
+  const DCM_GLOBAL double* a;              // A samples of this domain, [.][3]
   long long a_stride;           // doubles between steps (3) -- kept general
   // workspace (accumulation type of the projector products)
-  void* ppart;                  // [n_split][n_proj][2 n_orb] split-K partials
-  void* pmat;                   // [n_proj][2 n_orb]  P = h^3 B^H u
-  void* qmat;                   // [2 n_proj][ldq] real form of coef D P
+  DCM_GLOBAL void* ppart;                  // [n_split][n_proj][2 n_orb] split-K partials
+  DCM_GLOBAL void* pmat;                   // [n_proj][2 n_orb]  P = h^3 B^H u
+  DCM_GLOBAL void* qmat;                   // [2 n_proj][ldq] real form of coef D P
   long long ldq;                // row stride of qmat: 2 n_orb rounded up to 4
-  void* qmat3;                  // FP32: [3][n_proj][ldq3] Re Q, Im Q - Re Q, Re Q + Im Q (null otherwise)
+  DCM_GLOBAL void* qmat3;                  // FP32: [3][n_proj][ldq3] Re Q, Im Q - Re Q, Re Q + Im Q (null otherwise)
   long long ldq3;               // n_orb rounded up to 4
-  double* e_loc;                // [n_stencil_items] local-energy partials
-  double* e_nl;                 // [n_reduce_items] nonlocal-energy partials
-  double* g_part;               // [n_grad_items][3] gradient partials
+  DCM_GLOBAL double* e_loc;                // [n_stencil_items] local-energy partials
+  DCM_GLOBAL double* e_nl;                 // [n_reduce_items] nonlocal-energy partials
+  DCM_GLOBAL double* g_part;               // [n_grad_items][3] gradient partials
   int n_split;                  // projection split-K count
   int split_len;                // grid points per split
   int zseg;                     // z planes per stencil sweep segment
@@ -57,24 +74,24 @@ struct DomDesc {
   int n_chunks;                 // orbital chunks of the stencil sweep
   int item0_rows;               // first item of this domain in its row-block launch
   int n_rows_blocks;            // row blocks (256 grid points) of the domain
-  double* cn_part;              // [n_rows_blocks][n_orb] column-norm partials
-  double* cn_inv;               // [n_orb] inverse column norms
-  void* dpart;                  // [n_chunks][N_g][4] density / current partials
+  DCM_GLOBAL double* cn_part;              // [n_rows_blocks][n_orb] column-norm partials
+  DCM_GLOBAL double* cn_inv;               // [n_orb] inverse column norms
+  DCM_GLOBAL void* dpart;                  // [n_chunks][N_g][4] density / current partials
   // per-step observables (may be null)
-  void* rho;                    // [.][N_g]
-  void* jcur;                   // [.][N_g][3]
-  double* energy;               // [.]
-  double* grad;                 // [3] gradient accumulator (adjoint)
-  double* overlap;              // [n_orb][n_orb] complex128
-  double* smat;                 // workspace [n_orb][n_orb] complex128 (cross overlap)
-  double* f_occ;                // [n_orb] occupations of the reference orbitals
-  double* n_exc;                // one value: electrons outside the reference span
+  DCM_GLOBAL void* rho;                    // [.][N_g]
+  DCM_GLOBAL void* jcur;                   // [.][N_g][3]
+  DCM_GLOBAL double* energy;               // [.]
+  DCM_GLOBAL double* grad;                 // [3] gradient accumulator (adjoint)
+  DCM_GLOBAL double* overlap;              // [n_orb][n_orb] complex128
+  DCM_GLOBAL double* smat;                 // workspace [n_orb][n_orb] complex128 (cross overlap)
+  DCM_GLOBAL double* f_occ;                // [n_orb] occupations of the reference orbitals
+  DCM_GLOBAL double* n_exc;                // one value: electrons outside the reference span
   int item0_occ;                // first item of this domain in its occupation-row launch
   // split-precision operands (16-bit hi and lo planes), null otherwise
-  void* bs_hi; void* bs_lo;     // [N_g][ldbs]       projectors as stored
-  void* bt_hi; void* bt_lo;     // [n_proj][ldbt]    projectors transposed
-  void* qt_hi; void* qt_lo;     // [2 n_orb][ldqt]   transposed real form of coef D P
-  unsigned* maxbits;            // [4]: max |B|, max |u|, max |Q'| as float bits (FP16 scaling)
+  DCM_GLOBAL void* bs_hi; DCM_GLOBAL void* bs_lo;    // [N_g][ldbs]       projectors as stored
+  DCM_GLOBAL void* bt_hi; DCM_GLOBAL void* bt_lo;    // [n_proj][ldbt]    projectors transposed
+  DCM_GLOBAL void* qt_hi; DCM_GLOBAL void* qt_lo;    // [2 n_orb][ldqt]   transposed real form of coef D P
+  DCM_GLOBAL unsigned* maxbits;            // [4]: max |B|, max |u|, max |Q'| as float bits (FP16 scaling)
   long long ldbs, ldbt, ldqt;   // row strides (halves) of bs, bt, qt: multiples of 8, zero padded
 };
 

@@ -56,13 +56,20 @@ size_t real_size(int prec) { return is_fp64(prec) ? 8 : 4; }
 // ---------------------------------------------------------------------------
 struct StencilVariant { int oc, tx, ty, nt; };
 // variants 6 and 7 prefetch two planes ahead with a double-buffered LDS plane
+// variants 8-11 fetch each plane's halo with its interior (k_stencil_sweep3):
+// 8 and 10 as allocated, 9 and 11 held to 4 waves per SIMD; 10 and 11 write
+// with non-temporal stores
 const StencilVariant kStencilF32[] = {{16, 16, 8, 256}, {8, 16, 8, 256}, {16, 8, 8, 256},
                                       {4, 16, 16, 256}, {16, 8, 8, 512}, {16, 16, 8, 512},
-                                      {16, 8, 8, 512}, {16, 8, 8, 256}};
+                                      {16, 8, 8, 512}, {16, 8, 8, 256}, {16, 8, 8, 512},
+                                      {16, 8, 8, 512}, {16, 8, 8, 512}, {16, 8, 8, 512}};
 const StencilVariant kStencilF64[] = {{8, 16, 8, 256}, {8, 8, 8, 256}, {4, 16, 8, 256},
                                       {16, 8, 4, 256}, {8, 8, 8, 512}, {8, 16, 8, 512},
-                                      {8, 8, 8, 512}, {8, 8, 8, 256}};
-constexpr int kNStencil = 8;
+                                      {8, 8, 8, 512}, {8, 8, 8, 256}, {8, 8, 8, 512},
+                                      {8, 8, 8, 512}, {8, 8, 8, 512}, {8, 8, 8, 512}};
+constexpr int kNStencil = 12;
+constexpr int kFirstSweep3 = 8;
+constexpr int kStencilFallback = 2;
 constexpr int kStencilDefault = 2;
 // z planes per sweep segment: 0 = chosen from the block count, else fixed
 const int kZsegOpt[] = {0, 8, 16, 32, 1 << 20};
@@ -84,9 +91,13 @@ constexpr int kProjKG = 16;
 
 std::atomic<int> g_tune[4] = {{-1}, {-1}, {-1}, {-1}};
 
-int stencil_variant(const dcmesh_domain&, int) {
+// The sweep3 variants address a plane of u with 32-bit byte offsets; a domain
+// whose plane spans 2^32 bytes or more uses the default sweep instead.
+int stencil_variant(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_STENCIL].load();
-  return t >= 0 ? t : kStencilDefault;
+  const int v = t >= 0 ? t : kStencilDefault;
+  const long long plane_bytes = (long long)d.nx * d.ny * d.n_orb * (is_fp64(prec) ? 16 : 8);
+  return (v >= kFirstSweep3 && plane_bytes >= (1LL << 32)) ? kStencilFallback : v;
 }
 // FP32 projector products load rows with 16-byte vectors when every row
 // length is a multiple of 4 floats, else with 8-byte (one complex) vectors;
@@ -230,8 +241,8 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
 
   // work lists
   // stencil launches are keyed by (radius, tile variant): variant + 4 r
-  auto sv = [&](int i) { return stencil_variant(doms[i], prec) + 8 * (doms[i].fd_order / 2); };
-  auto stile = [&](int v) { return is_fp64(prec) ? kStencilF64[v % 8] : kStencilF32[v % 8]; };
+  auto sv = [&](int i) { return stencil_variant(doms[i], prec) + 16 * (doms[i].fd_order / 2); };
+  auto stile = [&](int v) { return is_fp64(prec) ? kStencilF64[v % 16] : kStencilF32[v % 16]; };
   long long stencil_blocks_xy = 0;
   for (int i = 0; i < n_dom; ++i) {
     const StencilVariant t = stile(sv(i));
@@ -409,30 +420,30 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
   for (int i = 0; i < n_dom; ++i) {
     DomDesc& D = P.desc[i];
     const size_t psi_bytes = (size_t)D.n_grid * D.n_orb * cs;
-    for (int s = SLOT_B0; s <= SLOT_B4; ++s) D.slot[s] = take(psi_bytes);
+    for (int s = SLOT_B0; s <= SLOT_B4; ++s) D.slot[s] = as_global(take(psi_bytes));
     const size_t no2 = 2 * (size_t)D.n_orb;
     const size_t part = std::max((size_t)D.n_split * D.n_proj * no2 * acc, (size_t)D.n_split * D.n_orb * no2 * 8);
-    D.ppart = take(part);
-    D.pmat = take((size_t)D.n_proj * no2 * acc);
-    D.qmat = take(2 * (size_t)D.n_proj * D.ldq * acc);
+    D.ppart = as_global(take(part));
+    D.pmat = as_global(take((size_t)D.n_proj * no2 * acc));
+    D.qmat = as_global(take(2 * (size_t)D.n_proj * D.ldq * acc));
     // three-product (Gauss) planes of coef D P for the FP32 correction
-    D.qmat3 = prec == DCMESH_FP32 ? take(3 * (size_t)D.n_proj * D.ldq3 * sizeof(float)) : nullptr;
-    D.e_loc = (double*)take(sizeof(double) * (size_t)std::max<long long>(D.n_e_loc, stencil_bound(D)));
-    D.e_nl = (double*)take(sizeof(double) * std::max(1, D.n_e_nl));
-    D.g_part = (double*)take(3 * sizeof(double) * std::max(1, D.n_g_part));
+    D.qmat3 = as_global(prec == DCMESH_FP32 ? take(3 * (size_t)D.n_proj * D.ldq3 * sizeof(float)) : (char*)nullptr);
+    D.e_loc = as_global((double*)take(sizeof(double) * (size_t)std::max<long long>(D.n_e_loc, stencil_bound(D))));
+    D.e_nl = as_global((double*)take(sizeof(double) * std::max(1, D.n_e_nl)));
+    D.g_part = as_global((double*)take(3 * sizeof(double) * std::max(1, D.n_g_part)));
     // sized for the smallest orbital chunk of any stencil variant, so the
     // workspace does not depend on the tile choice
-    D.dpart = take((size_t)cdiv(D.n_orb, 4) * D.n_grid * 4 * rs);
-    D.cn_part = (double*)take(sizeof(double) * (size_t)D.n_rows_blocks * D.n_orb);
-    D.cn_inv = (double*)take(sizeof(double) * D.n_orb);
-    D.smat = (double*)take(16 * (size_t)D.n_orb * D.n_orb);
+    D.dpart = as_global(take((size_t)cdiv(D.n_orb, 4) * D.n_grid * 4 * rs));
+    D.cn_part = as_global((double*)take(sizeof(double) * (size_t)D.n_rows_blocks * D.n_orb));
+    D.cn_inv = as_global((double*)take(sizeof(double) * D.n_orb));
+    D.smat = as_global((double*)take(16 * (size_t)D.n_orb * D.n_orb));
     if (is_split(prec) && D.n_proj > 0) {
       const size_t nbs = (size_t)D.n_grid * D.ldbs * 2, nbt = (size_t)D.n_proj * D.ldbt * 2;   // 16-bit values
-      D.bs_hi = take(nbs); D.bs_lo = take(nbs);
-      D.bt_hi = take(nbt); D.bt_lo = take(nbt);
+      D.bs_hi = as_global(take(nbs)); D.bs_lo = as_global(take(nbs));
+      D.bt_hi = as_global(take(nbt)); D.bt_lo = as_global(take(nbt));
       const size_t nq = (size_t)2 * D.n_orb * D.ldqt * 2;
-      D.qt_hi = take(nq); D.qt_lo = take(nq);
-      D.maxbits = (unsigned*)take(4 * sizeof(unsigned));
+      D.qt_hi = as_global(take(nq)); D.qt_lo = as_global(take(nq));
+      D.maxbits = as_global((unsigned*)take(4 * sizeof(unsigned)));
     }
   }
   P.bytes_total = off;
@@ -599,7 +610,11 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
       case 4: k_stencil_sweep<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 5: k_stencil_sweep<T, R, 16, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 6: k_stencil_sweep2<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep2<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 7: k_stencil_sweep2<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 8: k_stencil_sweep3<T, R, 16, 8, 8, 512, false, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 9: k_stencil_sweep3<T, R, 16, 8, 8, 512, false, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 10: k_stencil_sweep3<T, R, 16, 8, 8, 512, true, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep3<T, R, 16, 8, 8, 512, true, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
     }
   } else {
     switch (L.variant) {
@@ -610,20 +625,24 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
       case 4: k_stencil_sweep<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 5: k_stencil_sweep<T, R, 8, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 6: k_stencil_sweep2<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep2<T, R, 8, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 7: k_stencil_sweep2<T, R, 8, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 8: k_stencil_sweep3<T, R, 8, 8, 8, 512, false, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 9: k_stencil_sweep3<T, R, 8, 8, 8, 512, false, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 10: k_stencil_sweep3<T, R, 8, 8, 8, 512, true, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep3<T, R, 8, 8, 8, 512, true, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
     }
   }
 }
 
-// Stencil launches are keyed by variant + 8 r, so every domain of a launch
+// Stencil launches are keyed by variant + 16 r, so every domain of a launch
 // shares the stencil radius.
 template <typename T>
 void launch_stencil(const Ctx& c, const StencilArgs& a) {
   ProfScope prof_(DCMESH_FAM_STENCIL, c.s);
   for (const Launch& L : c.P->stencil) {
     Launch l2 = L;
-    l2.variant = L.variant % 8;
-    switch (L.variant / 8) {
+    l2.variant = L.variant % 16;
+    switch (L.variant / 16) {
       case 1: launch_stencil_r<T, 1>(c, l2, a); break;
       case 2: launch_stencil_r<T, 2>(c, l2, a); break;
       default: launch_stencil_r<T, 3>(c, l2, a); break;
@@ -960,16 +979,16 @@ int step_impl(const dcmesh_domain* doms, int32_t n_dom, int32_t prec, const doub
   rc = prepare(cs, doms, n_dom, prec, work, work_bytes, s, flags, [&](Plan& P) {
     for (int i = 0; i < n_dom; ++i) {
       DomDesc& D = P.desc[i];
-      D.slot[SLOT_PSI] = doms[i].psi;
-      D.v = doms[i].v_loc;
-      D.proj = doms[i].proj;
-      D.d = doms[i].d;
-      D.occ = doms[i].occ;
-      D.a = a_dev + (a_per_domain ? (long long)i * a_stride * 3 : 0);
+      D.slot[SLOT_PSI] = as_global(doms[i].psi);
+      D.v = as_global(doms[i].v_loc);
+      D.proj = as_global(doms[i].proj);
+      D.d = as_global(doms[i].d);
+      D.occ = as_global(doms[i].occ);
+      D.a = as_global(a_dev + (a_per_domain ? (long long)i * a_stride * 3 : 0));
       if (obs) {
-        D.rho = obs[i].rho;
-        D.jcur = obs[i].j;
-        D.energy = obs[i].energy;
+        D.rho = as_global(obs[i].rho);
+        D.jcur = as_global(obs[i].j);
+        D.energy = as_global(obs[i].energy);
       }
     }
   });
@@ -1051,12 +1070,12 @@ int dcmesh_step_eq2(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
   rc = prepare(cs, eq2.data(), n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
     for (int i = 0; i < n_dom; ++i) {
       DomDesc& D = P.desc[i];
-      D.slot[SLOT_PSI] = eq2[i].psi;
-      D.v = eq2[i].v_loc;
-      D.proj = eq2[i].proj;
-      D.d = eq2[i].d;
-      D.occ = eq2[i].occ;
-      D.a = a_dev + (a_per_domain ? (long long)i * a_stride * 3 : 0);
+      D.slot[SLOT_PSI] = as_global(eq2[i].psi);
+      D.v = as_global(eq2[i].v_loc);
+      D.proj = as_global(eq2[i].proj);
+      D.d = as_global(eq2[i].d);
+      D.occ = as_global(eq2[i].occ);
+      D.a = as_global(a_dev + (a_per_domain ? (long long)i * a_stride * 3 : 0));
     }
   });
   if (rc) return rc;
@@ -1087,17 +1106,17 @@ int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, 
   rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
     for (int i = 0; i < n_dom; ++i) {
       DomDesc& D = P.desc[i];
-      D.slot[SLOT_PSI] = doms[i].psi;
-      D.slot[SLOT_HPSI] = out[i].hpsi_occ ? out[i].hpsi_occ : D.slot[SLOT_B0];
-      D.v = doms[i].v_loc;
-      D.proj = doms[i].proj;
-      D.d = doms[i].d;
-      D.occ = doms[i].occ;
-      D.a = a_dev + (a_per_domain ? (long long)i * 3 : 0);
-      D.rho = out[i].rho;
-      D.jcur = out[i].j;
-      D.energy = out[i].energy;
-      D.overlap = out[i].overlap;
+      D.slot[SLOT_PSI] = as_global(doms[i].psi);
+      D.slot[SLOT_HPSI] = out[i].hpsi_occ ? as_global(out[i].hpsi_occ) : D.slot[SLOT_B0];
+      D.v = as_global(doms[i].v_loc);
+      D.proj = as_global(doms[i].proj);
+      D.d = as_global(doms[i].d);
+      D.occ = as_global(doms[i].occ);
+      D.a = as_global(a_dev + (a_per_domain ? (long long)i * 3 : 0));
+      D.rho = as_global(out[i].rho);
+      D.jcur = as_global(out[i].j);
+      D.energy = as_global(out[i].energy);
+      D.overlap = as_global(out[i].overlap);
     }
   });
   if (rc) return rc;
@@ -1131,12 +1150,12 @@ int dcmesh_occupations(const dcmesh_domain* doms, int32_t n_dom, int32_t precisi
   rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
     for (int i = 0; i < n_dom; ++i) {
       DomDesc& D = P.desc[i];
-      D.slot[SLOT_PSI] = doms[i].psi;
-      D.slot[SLOT_LAMBDA] = const_cast<void*>(psi0[i]);
-      D.occ = doms[i].occ;
-      D.overlap = overlap && overlap[i] ? overlap[i] : D.smat;
-      D.f_occ = f_out[i];
-      D.n_exc = n_exc + i;
+      D.slot[SLOT_PSI] = as_global(doms[i].psi);
+      D.slot[SLOT_LAMBDA] = as_global(const_cast<void*>(psi0[i]));
+      D.occ = as_global(doms[i].occ);
+      D.overlap = overlap && overlap[i] ? as_global(overlap[i]) : D.smat;
+      D.f_occ = as_global(f_out[i]);
+      D.n_exc = as_global(n_exc + i);
     }
   });
   if (rc) return rc;
@@ -1159,14 +1178,14 @@ int dcmesh_adjoint_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
   rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
     for (int i = 0; i < n_dom; ++i) {
       DomDesc& D = P.desc[i];
-      D.slot[SLOT_PSI] = doms[i].psi;
-      D.slot[SLOT_LAMBDA] = lambda[i];
-      D.v = doms[i].v_loc;
-      D.proj = doms[i].proj;
-      D.d = doms[i].d;
-      D.occ = doms[i].occ;
-      D.a = a_dev + (a_per_domain ? (long long)i * 3 : 0);
-      D.grad = grad_dev + (a_per_domain ? (long long)i * 3 : 0);
+      D.slot[SLOT_PSI] = as_global(doms[i].psi);
+      D.slot[SLOT_LAMBDA] = as_global(lambda[i]);
+      D.v = as_global(doms[i].v_loc);
+      D.proj = as_global(doms[i].proj);
+      D.d = as_global(doms[i].d);
+      D.occ = as_global(doms[i].occ);
+      D.a = as_global(a_dev + (a_per_domain ? (long long)i * 3 : 0));
+      D.grad = as_global(grad_dev + (a_per_domain ? (long long)i * 3 : 0));
     }
   });
   if (rc) return rc;

@@ -440,6 +440,207 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep2(const DomDesc* __restrict
   }
 }
 
+// Same sweep with every global read of a plane issued in one step: the halo
+// strips of plane z + R + 1 are fetched together with its interior (the queue
+// head) and wait in a register queue of R planes until that plane becomes the
+// centre.  Neighbouring tiles fetch the same plane at about the same time, so
+// the strips are served from L2 instead of being fetched again from memory a
+// few planes later.  The centre plane is double-buffered in LDS (one barrier
+// per plane).  When the base buffer is u itself (the first Horner stage) the
+// base term is the queue's centre and is not read again.  Addresses are a
+// per-plane base (uniform) plus a fixed 32-bit byte offset per column, which
+// requires a plane of u, nx ny n_orb complex values, to span < 2^32 bytes.
+// NTS: write the output with non-temporal stores.  MINW: minimum waves per
+// SIMD asked of the register allocator.
+template <typename T, int R, int OC, int TX, int TY, int NT, bool NTS, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_stencil_sweep3(const DomDesc* __restrict__ doms,
+                                                       const Item* __restrict__ items,
+                                                       StencilArgs args) {
+  using C = Cplx<T>;
+  using Cfg = SweepCfg<R, OC, TX, TY, NT>;
+  constexpr int KP = Cfg::kPer, KQ = Cfg::kQ, KH = Cfg::kHPer;
+  constexpr int PLANE = Cfg::kLY * Cfg::kLX * OC;
+  __shared__ C lds[2 * PLANE];
+  __shared__ double red[NT / kWave];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int nx = D.nx, ny = D.ny, nz = D.nz, no = D.n_orb;
+  const int x0 = it.a * TX, y0 = it.b * TY;
+  const int chunk = it.c & 0xffff;
+  const int zseg = it.c >> 16, oc0 = chunk * OC;
+  const int z_begin = zseg * D.zseg, z_end = min(z_begin + D.zseg, nz);
+
+  const bool base_is_u = args.base_slot == args.u_slot;
+  const char* __restrict__ ub = (const char*)D.slot[args.u_slot];
+  const char* __restrict__ bb =
+      (args.base_slot < SLOT_NONE && !base_is_u) ? (const char*)D.slot[args.base_slot] : nullptr;
+  char* __restrict__ ob = (char*)D.slot[args.out_slot];
+  const char* __restrict__ vb = (const char*)D.v;
+  const T* __restrict__ occ = (const T*)D.occ;
+  const long long plane = (long long)nx * ny;
+  const long long pbytes = plane * no * (long long)sizeof(C);      // one plane of u
+  const long long vbytes = plane * (long long)sizeof(T);           // one plane of V
+
+  const StencilW<T> w = stencil_weights<T>(D, args.step);
+  const T cre = (T)args.cre, cim = (T)args.cim;
+
+  const int o = threadIdx.x % OC;
+  const int tc = threadIdx.x / OC;
+  const int n = oc0 + o;
+  const bool n_ok = n < no;
+  const int nl = n_ok ? n : no - 1;        // lanes past the last orbital read a valid element
+  const T fn = n_ok ? occ[n] : (T)0;
+
+  int lxk[KP], lyk[KP];
+  unsigned co[KP], cv[KP];                 // byte offsets of the column in a plane of u / of V
+  bool ok[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int col = tc + k * Cfg::kThrCols;
+    lxk[k] = col % TX;
+    lyk[k] = col / TX;
+    const int x = x0 + lxk[k], y = y0 + lyk[k];
+    ok[k] = n_ok && x < nx && y < ny;
+    const unsigned gc = (unsigned)(wrap(y, ny) * nx + wrap(x, nx));
+    co[k] = (gc * (unsigned)no + (unsigned)nl) * (unsigned)sizeof(C);
+    cv[k] = gc * (unsigned)sizeof(T);
+  }
+  int hl[KH];
+  unsigned ho[KH];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    const int hidx = tc + k * Cfg::kThrCols;
+    int lx = R, ly = R;
+    if (hidx < Cfg::kH) halo_xy<R, TX, TY>(hidx, lx, ly);
+    hl[k] = hidx < Cfg::kH ? (ly * Cfg::kLX + lx) * OC + o : -1;
+    const unsigned gc = (unsigned)(wrap(y0 + ly - R, ny) * nx + wrap(x0 + lx - R, nx));
+    ho[k] = (gc * (unsigned)no + (unsigned)nl) * (unsigned)sizeof(C);
+  }
+  auto at = [&](const char* b, int z, unsigned off) -> C {
+    return *(const C*)(b + (long long)z * pbytes + off);
+  };
+  auto vat = [&](int z, unsigned off) -> T { return *(const T*)(vb + (long long)z * vbytes + off); };
+
+  C q[KP][KQ];          // q[k][s] = plane z - R + s
+  C hq[KH][R + 1];      // hq[k][j] = halo of plane z + 1 + j; j = R receives the prefetch
+  C qn[KP];             // prefetch of the queue head, plane z + R + 1
+  C bcur[KP], bpf[KP];
+  T vcur[KP], vpf[KP];
+
+  // prologue: the queue of z_begin; its centre plane (interior and halo) into
+  // LDS buffer 0; the halo of the next R planes into the halo queue
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+#pragma unroll
+    for (int s = 0; s < KQ; ++s) q[k][s] = at(ub, wrap(z_begin - R + s, nz), co[k]);
+    bcur[k] = bb ? at(bb, z_begin, co[k]) : C{0, 0};
+    vcur[k] = vat(z_begin, cv[k]);
+    lds[((lyk[k] + R) * Cfg::kLX + (lxk[k] + R)) * OC + o] = q[k][R];
+  }
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    if (hl[k] >= 0) lds[hl[k]] = at(ub, z_begin, ho[k]);
+#pragma unroll
+    for (int j = 0; j < R; ++j) hq[k][j] = at(ub, wrap(z_begin + 1 + j, nz), ho[k]);
+  }
+  __syncthreads();
+
+  double e_acc = 0.0;
+  for (int z = z_begin; z < z_end; ++z) {
+    const bool more = z + 1 < z_end;
+    const C* L = lds + ((z - z_begin) & 1) * PLANE;
+    if (more) {
+      const int zq = wrap(z + 1 + R, nz);
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        qn[k] = at(ub, zq, co[k]);
+        bpf[k] = bb ? at(bb, z + 1, co[k]) : C{0, 0};
+        vpf[k] = vat(z + 1, cv[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < KH; ++k) hq[k][R] = at(ub, zq, ho[k]);
+    }
+
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int cx = lxk[k] + R, cy = lyk[k] + R;
+      const C c0 = q[k][R];
+      C S{0, 0}, G[3] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+      for (int m = 1; m <= R; ++m) {
+        const C xp = L[(cy * Cfg::kLX + cx + m) * OC + o], xm = L[(cy * Cfg::kLX + cx - m) * OC + o];
+        const C yp = L[((cy + m) * Cfg::kLX + cx) * OC + o], ym = L[((cy - m) * Cfg::kLX + cx) * OC + o];
+        const C zp = q[k][R + m], zm = q[k][R - m];
+        const T al = w.alpha[m - 1], am = w.a1[m - 1];
+        S.re += al * ((xp.re + xm.re) + (yp.re + ym.re) + (zp.re + zm.re));
+        S.im += al * ((xp.im + xm.im) + (yp.im + ym.im) + (zp.im + zm.im));
+        G[0].re += am * (xp.re - xm.re); G[0].im += am * (xp.im - xm.im);
+        G[1].re += am * (yp.re - ym.re); G[1].im += am * (yp.im - ym.im);
+        G[2].re += am * (zp.re - zm.re); G[2].im += am * (zp.im - zm.im);
+      }
+      const T cvk = w.centre + vcur[k];
+      C acc{S.re + cvk * c0.re + (w.A[0] * G[0].im + w.A[1] * G[1].im + w.A[2] * G[2].im),
+            S.im + cvk * c0.im - (w.A[0] * G[0].re + w.A[1] * G[1].re + w.A[2] * G[2].re)};
+      if (args.want_density) {
+        T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
+                   fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+        const int x = x0 + lxk[k], y = y0 + lyk[k];
+        if (o == 0 && x < nx && y < ny) {
+          const long long g = (long long)z * plane + (long long)(cv[k] / sizeof(T));
+          T* dp = (T*)D.dpart + ((long long)chunk * D.n_grid + g) * 4;
+          dp[0] = dv[0]; dp[1] = dv[1]; dp[2] = dv[2]; dp[3] = dv[3];
+        }
+      }
+      if (ok[k]) {
+        if (args.want_energy) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
+        if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
+        const C b = base_is_u ? c0 : bcur[k];
+        C r{cre * acc.re - cim * acc.im + b.re, cre * acc.im + cim * acc.re + b.im};
+        C* dst = (C*)(ob + (long long)z * pbytes + co[k]);
+        if constexpr (NTS) {
+          using V2 = T __attribute__((ext_vector_type(2)));
+          V2 x2;
+          x2.x = r.re;
+          x2.y = r.im;
+          __builtin_nontemporal_store(x2, (V2*)dst);
+        } else {
+          *dst = r;
+        }
+      }
+    }
+    if (!more) break;
+    // plane z + 1 becomes the centre: its interior (queue slot R + 1) and halo
+    // (halo-queue slot 0) go to the other LDS buffer, whose last readers
+    // finished before the previous barrier
+    C* Ln = lds + ((z + 1 - z_begin) & 1) * PLANE;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+#pragma unroll
+      for (int s = 0; s < KQ - 1; ++s) q[k][s] = q[k][s + 1];
+      q[k][KQ - 1] = qn[k];
+      bcur[k] = bpf[k];
+      vcur[k] = vpf[k];
+      Ln[((lyk[k] + R) * Cfg::kLX + (lxk[k] + R)) * OC + o] = q[k][R];
+    }
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+      if (hl[k] >= 0) Ln[hl[k]] = hq[k][0];
+#pragma unroll
+      for (int j = 0; j < R; ++j) hq[k][j] = hq[k][j + 1];
+    }
+    __syncthreads();
+  }
+  if (args.want_energy) {
+    const double s = block_sum<double, NT / kWave>(e_acc, red);
+    if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+  }
+}
+
 // rho[g] = sum_chunks dpart[c][g][0];  j[g][d] = sum_chunks dpart[c][g][1 + d] + A_d rho.
 // Items: (dom, block of 256 grid points).  step: A sample; obs: output row.
 template <typename T>

@@ -256,6 +256,64 @@ def test_tile_variants_agree(api, variant):
     assert rel_fro(_np(g.psi), ref) < TOL_PSI["fp32"]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("variant", list(range(12)))
+def test_every_stencil_variant_matches_oracle(api, variant, order, precision):
+    """Each stencil tile variant, at each FD order, on a ragged 19 x 13 x 21
+    domain of 21 orbitals (partial x/y tiles and a partial orbital chunk);
+    two steps with rho, j and E so every Horner stage and the fused density
+    and energy partials run."""
+    torch = _torch()
+    n_var = api.tuning_options("stencil")
+    if variant >= n_var:
+        pytest.skip("variant not built")
+    dom = _ragged(seed=41, order=order)
+    a_mid = _field(2)
+    od = oracle_inputs(dom, precision)
+    ref, obs = P.propagate(od, a_mid, 0.02, od.psi, want_rho=True, want_j=True, want_energy=True)
+    g = to_device(dom, precision)
+    ws = api.Workspace.for_domains([g], precision)
+    rd = torch.float64 if precision == "fp64" else torch.float32
+    rho = torch.zeros(2, dom.n_grid, dtype=rd, device="cuda")
+    j = torch.zeros(2, dom.n_grid, 3, dtype=rd, device="cuda")
+    e = torch.zeros(2, dtype=torch.float64, device="cuda")
+    try:
+        api.set_tuning("stencil", variant)
+        api.step([g], a_tensor(a_mid), 0.02, 2, precision, ws, obs=[dict(rho=rho, j=j, energy=e)])
+        torch.cuda.synchronize()
+    finally:
+        api.set_tuning("stencil", -1)
+    tol = TOL_PSI[precision]
+    assert rel_fro(_np(g.psi), ref) < tol
+    assert rel_fro(_np(rho), obs["rho"]) < tol
+    assert rel_fro(_np(j), obs["j"]) < tol * 10
+    assert np.abs(_np(e) - obs["energy"]).max() < tol * np.abs(obs["energy"]).max()
+
+
+@pytest.mark.parametrize("zseg", [1, 2, 3, 4])
+def test_every_z_segment_choice_matches_oracle(api, zseg):
+    """Fixed z segments of 8, 16, 32 planes and whole columns, on a 37-plane
+    domain (ragged last segment), with the default and the sweep3 tiles."""
+    torch = _torch()
+    dom = make_domain(42, (12, 11, 37), 9, 2, proj_per_atom=8, h=0.4, fd_order=6)
+    a_mid = _field(2)
+    od = oracle_inputs(dom, "fp32")
+    ref, _ = P.propagate(od, a_mid, 0.02, od.psi)
+    for variant in (-1, 8):
+        g = to_device(dom, "fp32")
+        ws = api.Workspace.for_domains([g], "fp32")
+        try:
+            api.set_tuning("zseg", zseg)
+            api.set_tuning("stencil", variant)
+            api.step([g], a_tensor(a_mid), 0.02, 2, "fp32", ws)
+            torch.cuda.synchronize()
+        finally:
+            api.set_tuning("zseg", -1)
+            api.set_tuning("stencil", -1)
+        assert rel_fro(_np(g.psi), ref) < TOL_PSI["fp32"], variant
+
+
 def test_check_finite_flags_nan(api):
     torch = _torch()
     from paper_2509_00966_amd._lib import DcmeshError
