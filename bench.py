@@ -16,7 +16,9 @@ records around every launch on the call's stream (DCMESH_FLAG_PROFILE) during
 the timed steps.
 """
 import argparse
+import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -120,7 +122,10 @@ def main():
     ms_step = elapsed * 1e3 / K
     updates = ng * no * 4 * K / elapsed
     flops_gemm = 8.0 * ng * no * npj              # per projection or correction launch
-    bytes_stencil = ng * no * 24.0 + ng * 4.0     # read u, read psi, write out, read V
+    # per launch, averaged over the four Horner stages: the first reads psi once
+    # (it is both u and the base), the other three read u and psi; all write
+    # out and read V
+    bytes_stencil = ng * no * (16.0 + 3 * 24.0) / 4 + ng * 4.0
     bytes_gemm = ng * npj * 8.0 + ng * no * 8.0   # projectors once (FP32 or hi+lo 16-bit), orbitals once
     roofline, kernels = roofline_of(prof, flops_gemm, bytes_stencil, prec, bytes_gemm)
 
@@ -195,8 +200,43 @@ def roofline_of(prof, flops_gemm, bytes_stencil, prec, bytes_gemm=None):
     dom_fam = max((f for f in kernels if "peak" in kernels[f]), key=lambda f: kernels[f]["total_ms"])
     dk = kernels[dom_fam]
     roof = {"kernel": dom_fam, "bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
-            "unit": dk["unit"], "frac": dk["frac"], "traffic": None}
+            "unit": dk["unit"], "frac": dk["frac"], "traffic": measured_traffic(dom_fam, prec)}
     return roof, kernels
+
+
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic_64cube_128orb_512proj.md")
+KERNEL_SOURCES = ("common.hpp", "stencil.hpp", "gemm.hpp", "gemm_split.hpp", "reduce.hpp", "dcmesh.hip")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_00966_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family, prec):
+    """HBM bytes per launch of a kernel family on the 64^3 workload, from the
+    FETCH_SIZE / WRITE_SIZE counter table in profiles/ (each counter scaled by
+    what it reads for a copy of known size).  None when the table was taken
+    from kernel sources other than the ones built here."""
+    try:
+        with open(TRAFFIC_TABLE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"kernel source hash: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 6 and cells[0] == family and cells[1] == prec:
+            try:
+                return float(cells[5])
+            except ValueError:
+                return None
+    return None
 
 
 def run_batched(args):
@@ -253,7 +293,7 @@ def run_batched(args):
     steps = reps * S
     po = sum(d.n_grid * d.n_orb for d in doms)
     flops_gemm = sum(8.0 * d.n_grid * d.n_orb * d.n_proj for d in doms)
-    bytes_stencil = sum(d.n_grid * d.n_orb * 24.0 + d.n_grid * 4.0 for d in doms)
+    bytes_stencil = sum(d.n_grid * d.n_orb * (16.0 + 3 * 24.0) / 4 + d.n_grid * 4.0 for d in doms)
     bytes_gemm = sum(d.n_grid * d.n_proj * 8.0 + d.n_grid * d.n_orb * 8.0 for d in doms)
     roof, kernels = roofline_of(prof, flops_gemm, bytes_stencil, prec, bytes_gemm)
     out = {

@@ -56,21 +56,22 @@ size_t real_size(int prec) { return is_fp64(prec) ? 8 : 4; }
 // ---------------------------------------------------------------------------
 struct StencilVariant { int oc, tx, ty, nt; };
 // variants 6 and 7 prefetch two planes ahead with a double-buffered LDS plane
-// variants 8-11 fetch each plane's halo with its interior (k_stencil_sweep3):
-// 8 and 10 as allocated, 9 and 11 held to 4 waves per SIMD; 10 and 11 write
-// with non-temporal stores
+// variants 8-11 fetch each plane's halo with its interior: 8 with the queues
+// shifted per plane (k_stencil_sweep3), 9-11 with unrolled register rings
+// (k_stencil_sweep4)
 const StencilVariant kStencilF32[] = {{16, 16, 8, 256}, {8, 16, 8, 256}, {16, 8, 8, 256},
                                       {4, 16, 16, 256}, {16, 8, 8, 512}, {16, 16, 8, 512},
                                       {16, 8, 8, 512}, {16, 8, 8, 256}, {16, 8, 8, 512},
-                                      {16, 8, 8, 512}, {16, 8, 8, 512}, {16, 8, 8, 512}};
+                                      {16, 8, 8, 512}, {16, 8, 8, 256}, {16, 16, 8, 512}};
 const StencilVariant kStencilF64[] = {{8, 16, 8, 256}, {8, 8, 8, 256}, {4, 16, 8, 256},
                                       {16, 8, 4, 256}, {8, 8, 8, 512}, {8, 16, 8, 512},
                                       {8, 8, 8, 512}, {8, 8, 8, 256}, {8, 8, 8, 512},
-                                      {8, 8, 8, 512}, {8, 8, 8, 512}, {8, 8, 8, 512}};
+                                      {8, 8, 8, 512}, {8, 8, 8, 256}, {8, 16, 8, 512}};
 constexpr int kNStencil = 12;
 constexpr int kFirstSweep3 = 8;
 constexpr int kStencilFallback = 2;
-constexpr int kStencilDefault = 2;
+constexpr int kStencilDefaultF32 = 11;   // measured best at 64^3 / 128 orbitals
+constexpr int kStencilDefaultF64 = 2;    // the 16-wide FP64 ring sweep spills
 // z planes per sweep segment: 0 = chosen from the block count, else fixed
 const int kZsegOpt[] = {0, 8, 16, 32, 1 << 20};
 constexpr int kNZseg = 5;
@@ -95,7 +96,7 @@ std::atomic<int> g_tune[4] = {{-1}, {-1}, {-1}, {-1}};
 // whose plane spans 2^32 bytes or more uses the default sweep instead.
 int stencil_variant(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_STENCIL].load();
-  const int v = t >= 0 ? t : kStencilDefault;
+  const int v = t >= 0 ? t : (is_fp64(prec) ? kStencilDefaultF64 : kStencilDefaultF32);
   const long long plane_bytes = (long long)d.nx * d.ny * d.n_orb * (is_fp64(prec) ? 16 : 8);
   return (v >= kFirstSweep3 && plane_bytes >= (1LL << 32)) ? kStencilFallback : v;
 }
@@ -262,7 +263,9 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     if (zt > 0) {
       D.zseg = std::min(d.nz, kZsegOpt[zt]);
     } else {
-      const long long want = std::max<long long>(1, cdiv(1024, std::max<long long>(1, stencil_blocks_xy)));
+      // whole z columns (no re-read of the 2r boundary planes) once the
+      // column tiles give every CU a block; shorter segments only to fill it
+      const long long want = std::max<long long>(1, cdiv(256, std::max<long long>(1, stencil_blocks_xy)));
       D.zseg = (int)std::min<long long>(d.nz, std::max<long long>(16, cdiv(d.nz, want)));
     }
     // split-K length depends on the domain alone, so a domain gives the same
@@ -611,10 +614,10 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
       case 5: k_stencil_sweep<T, R, 16, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 6: k_stencil_sweep2<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 7: k_stencil_sweep2<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
-      case 8: k_stencil_sweep3<T, R, 16, 8, 8, 512, false, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      case 9: k_stencil_sweep3<T, R, 16, 8, 8, 512, false, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      case 10: k_stencil_sweep3<T, R, 16, 8, 8, 512, true, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep3<T, R, 16, 8, 8, 512, true, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 8: k_stencil_sweep3<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 9: k_stencil_sweep4<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 10: k_stencil_sweep4<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep4<T, R, 16, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
     }
   } else {
     switch (L.variant) {
@@ -626,10 +629,10 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
       case 5: k_stencil_sweep<T, R, 8, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 6: k_stencil_sweep2<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 7: k_stencil_sweep2<T, R, 8, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
-      case 8: k_stencil_sweep3<T, R, 8, 8, 8, 512, false, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      case 9: k_stencil_sweep3<T, R, 8, 8, 8, 512, false, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      case 10: k_stencil_sweep3<T, R, 8, 8, 8, 512, true, 2><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
-      default: k_stencil_sweep3<T, R, 8, 8, 8, 512, true, 4><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 8: k_stencil_sweep3<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 9: k_stencil_sweep4<T, R, 8, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      case 10: k_stencil_sweep4<T, R, 8, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      default: k_stencil_sweep4<T, R, 8, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
     }
   }
 }

@@ -20,6 +20,8 @@
 // with shuffles); k_density_finish adds the chunks in order.
 #pragma once
 
+#include <utility>
+
 #include "common.hpp"
 
 namespace dcm {
@@ -450,10 +452,8 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep2(const DomDesc* __restrict
 // base term is the queue's centre and is not read again.  Addresses are a
 // per-plane base (uniform) plus a fixed 32-bit byte offset per column, which
 // requires a plane of u, nx ny n_orb complex values, to span < 2^32 bytes.
-// NTS: write the output with non-temporal stores.  MINW: minimum waves per
-// SIMD asked of the register allocator.
-template <typename T, int R, int OC, int TX, int TY, int NT, bool NTS, int MINW>
-__global__ __launch_bounds__(NT, MINW) void k_stencil_sweep3(const DomDesc* __restrict__ doms,
+template <typename T, int R, int OC, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_stencil_sweep3(const DomDesc* __restrict__ doms,
                                                        const Item* __restrict__ items,
                                                        StencilArgs args) {
   using C = Cplx<T>;
@@ -601,16 +601,7 @@ __global__ __launch_bounds__(NT, MINW) void k_stencil_sweep3(const DomDesc* __re
         if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
         const C b = base_is_u ? c0 : bcur[k];
         C r{cre * acc.re - cim * acc.im + b.re, cre * acc.im + cim * acc.re + b.im};
-        C* dst = (C*)(ob + (long long)z * pbytes + co[k]);
-        if constexpr (NTS) {
-          using V2 = T __attribute__((ext_vector_type(2)));
-          V2 x2;
-          x2.x = r.re;
-          x2.y = r.im;
-          __builtin_nontemporal_store(x2, (V2*)dst);
-        } else {
-          *dst = r;
-        }
+        *(C*)(ob + (long long)z * pbytes + co[k]) = r;
       }
     }
     if (!more) break;
@@ -639,6 +630,209 @@ __global__ __launch_bounds__(NT, MINW) void k_stencil_sweep3(const DomDesc* __re
     const double s = block_sum<double, NT / kWave>(e_acc, red);
     if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
   }
+}
+
+// The sweep of k_stencil_sweep3 with every plane-to-plane move taken out of
+// the loop.  The plane loop is unrolled by U = 2 (R + 1): the z queue becomes a
+// ring of U register slots (plane p in slot (p - z_begin + R) mod U), the halo
+// queue a ring of R + 1 slots, base and potential rings of two, and the LDS
+// centre plane alternates between two buffers, so every index is static and
+// each prefetch lands directly in the slot its plane will occupy.  GM selects
+// which gradient axes are formed (bit d: axis d): the x and y axes are skipped
+// when neither the field's component along them nor the current needs them.
+// Calls f(integral_constant<int, 0>, ..., integral_constant<int, U - 1>).
+template <typename F, int... Ps>
+__device__ __forceinline__ void with_phases(F&& f, std::integer_sequence<int, Ps...>) {
+  f(std::integral_constant<int, Ps>{}...);
+}
+
+template <typename T, int R, int OC, int TX, int TY, int NT, int GM>
+__device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, const StencilArgs& args,
+                                            const StencilW<T>& w, Cplx<T>* lds, double* red) {
+  using C = Cplx<T>;
+  using Cfg = SweepCfg<R, OC, TX, TY, NT>;
+  constexpr int KP = Cfg::kPer, KH = Cfg::kHPer, U = 2 * (R + 1), H = R + 1;
+  constexpr int PLANE = Cfg::kLY * Cfg::kLX * OC;
+
+  const int nx = D.nx, ny = D.ny, nz = D.nz, no = D.n_orb;
+  const int x0 = it.a * TX, y0 = it.b * TY;
+  const int chunk = it.c & 0xffff;
+  const int zseg = it.c >> 16, oc0 = chunk * OC;
+  const int z_begin = zseg * D.zseg, z_end = min(z_begin + D.zseg, nz);
+
+  const bool base_is_u = args.base_slot == args.u_slot;
+  const char* __restrict__ ub = (const char*)D.slot[args.u_slot];
+  const char* __restrict__ bb =
+      (args.base_slot < SLOT_NONE && !base_is_u) ? (const char*)D.slot[args.base_slot] : nullptr;
+  char* __restrict__ ob = (char*)D.slot[args.out_slot];
+  const char* __restrict__ vb = (const char*)D.v;
+  const T* __restrict__ occ = (const T*)D.occ;
+  const long long plane = (long long)nx * ny;
+  const long long pbytes = plane * no * (long long)sizeof(C);
+  const long long vbytes = plane * (long long)sizeof(T);
+  const T cre = (T)args.cre, cim = (T)args.cim;
+
+  const int o = threadIdx.x % OC;
+  const int tc = threadIdx.x / OC;
+  const int n = oc0 + o;
+  const bool n_ok = n < no;
+  const int nl = n_ok ? n : no - 1;
+  const T fn = n_ok ? occ[n] : (T)0;
+
+  int lc[KP];                      // LDS index of the column's centre cell
+  unsigned co[KP], cv[KP];
+  bool ok[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int col = tc + k * Cfg::kThrCols;
+    const int lx = col % TX, ly = col / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    ok[k] = n_ok && x < nx && y < ny;
+    lc[k] = ((ly + R) * Cfg::kLX + (lx + R)) * OC + o;
+    const unsigned gc = (unsigned)(wrap(y, ny) * nx + wrap(x, nx));
+    co[k] = (gc * (unsigned)no + (unsigned)nl) * (unsigned)sizeof(C);
+    cv[k] = gc * (unsigned)sizeof(T);
+  }
+  int hl[KH];
+  unsigned ho[KH];
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    const int hidx = tc + k * Cfg::kThrCols;
+    int lx = R, ly = R;
+    if (hidx < Cfg::kH) halo_xy<R, TX, TY>(hidx, lx, ly);
+    hl[k] = hidx < Cfg::kH ? (ly * Cfg::kLX + lx) * OC + o : -1;
+    const unsigned gc = (unsigned)(wrap(y0 + ly - R, ny) * nx + wrap(x0 + lx - R, nx));
+    ho[k] = (gc * (unsigned)no + (unsigned)nl) * (unsigned)sizeof(C);
+  }
+  auto at = [&](const char* b, int z, unsigned off) -> C {
+    return *(const C*)(b + (long long)z * pbytes + off);
+  };
+  auto vat = [&](int z, unsigned off) -> T { return *(const T*)(vb + (long long)z * vbytes + off); };
+
+  C q[KP][U];          // plane p in slot (p - z_begin + R) % U
+  C hq[KH][H];         // halo of plane p in slot (p - z_begin) % H
+  C bq[KP][2];         // base of plane p in slot (p - z_begin) % 2
+  T vq[KP][2];         // potential of plane p in slot (p - z_begin) % 2
+
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+#pragma unroll
+    for (int s = 0; s < 2 * R + 1; ++s) q[k][s] = at(ub, wrap(z_begin - R + s, nz), co[k]);
+    bq[k][0] = bb ? at(bb, z_begin, co[k]) : C{0, 0};
+    vq[k][0] = vat(z_begin, cv[k]);
+    lds[lc[k]] = q[k][R];
+  }
+#pragma unroll
+  for (int k = 0; k < KH; ++k) {
+    if (hl[k] >= 0) lds[hl[k]] = at(ub, z_begin, ho[k]);
+#pragma unroll
+    for (int j = 1; j <= R; ++j) hq[k][j] = at(ub, wrap(z_begin + j, nz), ho[k]);
+  }
+  __syncthreads();
+
+  double e_acc = 0.0;
+  // one plane at phase P = (z - z_begin) % U; false once the segment is done
+  auto plane_step = [&](auto PC, int z) -> bool {
+    constexpr int P = decltype(PC)::value;
+    const bool more = z + 1 < z_end;
+    if (more) {
+      const int zq = wrap(z + 1 + R, nz);
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        q[k][(P + 2 * R + 1) % U] = at(ub, zq, co[k]);
+        bq[k][(P + 1) % 2] = bb ? at(bb, z + 1, co[k]) : C{0, 0};
+        vq[k][(P + 1) % 2] = vat(z + 1, cv[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < KH; ++k) hq[k][P % H] = at(ub, zq, ho[k]);
+    }
+    const C* L = lds + (P % 2) * PLANE;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const C c0 = q[k][(P + R) % U];
+      C S{0, 0}, G[3] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+      for (int m = 1; m <= R; ++m) {
+        const C xp = L[lc[k] + m * OC], xm = L[lc[k] - m * OC];
+        const C yp = L[lc[k] + m * Cfg::kLX * OC], ym = L[lc[k] - m * Cfg::kLX * OC];
+        const C zp = q[k][(P + R + m) % U], zm = q[k][(P + R - m) % U];
+        const T al = w.alpha[m - 1], am = w.a1[m - 1];
+        S.re += al * ((xp.re + xm.re) + (yp.re + ym.re) + (zp.re + zm.re));
+        S.im += al * ((xp.im + xm.im) + (yp.im + ym.im) + (zp.im + zm.im));
+        if constexpr (GM & 1) { G[0].re += am * (xp.re - xm.re); G[0].im += am * (xp.im - xm.im); }
+        if constexpr (GM & 2) { G[1].re += am * (yp.re - ym.re); G[1].im += am * (yp.im - ym.im); }
+        if constexpr (GM & 4) { G[2].re += am * (zp.re - zm.re); G[2].im += am * (zp.im - zm.im); }
+      }
+      const T cvk = w.centre + vq[k][P % 2];
+      T agi = 0, agr = 0;                    // A.G (imaginary and real parts)
+      if constexpr (GM & 1) { agi += w.A[0] * G[0].im; agr += w.A[0] * G[0].re; }
+      if constexpr (GM & 2) { agi += w.A[1] * G[1].im; agr += w.A[1] * G[1].re; }
+      if constexpr (GM & 4) { agi += w.A[2] * G[2].im; agr += w.A[2] * G[2].re; }
+      C acc{S.re + cvk * c0.re + agi, S.im + cvk * c0.im - agr};
+      if constexpr (GM == 7) {
+        if (args.want_density) {
+          T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
+                     fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+          const int col = tc + k * Cfg::kThrCols;
+          const int x = x0 + col % TX, y = y0 + col / TX;
+          if (o == 0 && x < nx && y < ny) {
+            const long long g = (long long)z * plane + (long long)(cv[k] / sizeof(T));
+            T* dp = (T*)D.dpart + ((long long)chunk * D.n_grid + g) * 4;
+            dp[0] = dv[0]; dp[1] = dv[1]; dp[2] = dv[2]; dp[3] = dv[3];
+          }
+        }
+      }
+      if (ok[k]) {
+        if (args.want_energy) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
+        if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
+        const C b = base_is_u ? c0 : bq[k][P % 2];
+        *(C*)(ob + (long long)z * pbytes + co[k]) =
+            C{cre * acc.re - cim * acc.im + b.re, cre * acc.im + cim * acc.re + b.im};
+      }
+    }
+    if (!more) return false;
+    // plane z + 1 becomes the centre: its interior and halo go to the other
+    // LDS buffer, whose readers finished before the previous barrier
+    C* Ln = lds + ((P + 1) % 2) * PLANE;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) Ln[lc[k]] = q[k][(P + R + 1) % U];
+#pragma unroll
+    for (int k = 0; k < KH; ++k)
+      if (hl[k] >= 0) Ln[hl[k]] = hq[k][(P + 1) % H];
+    __syncthreads();
+    return true;
+  };
+  auto run = [&](auto... PCs) {
+    for (int z = z_begin; z < z_end; z += U)
+      if (!(plane_step(PCs, z + decltype(PCs)::value) && ...)) break;
+  };
+  with_phases(run, std::make_integer_sequence<int, U>{});
+  if (args.want_energy) {
+    const double s = block_sum<double, NT / kWave>(e_acc, red);
+    if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+  }
+}
+
+template <typename T, int R, int OC, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict__ doms,
+                                                       const Item* __restrict__ items,
+                                                       StencilArgs args) {
+  using Cfg = SweepCfg<R, OC, TX, TY, NT>;
+  __shared__ Cplx<T> lds[2 * Cfg::kLY * Cfg::kLX * OC];
+  __shared__ double red[NT / kWave];
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const StencilW<T> w = stencil_weights<T>(D, args.step);
+  if (args.want_density || w.A[0] != (T)0 || w.A[1] != (T)0)
+    sweep4_body<T, R, OC, TX, TY, NT, 7>(D, it, args, w, lds, red);
+  else if (w.A[2] != (T)0)
+    sweep4_body<T, R, OC, TX, TY, NT, 4>(D, it, args, w, lds, red);
+  else
+    sweep4_body<T, R, OC, TX, TY, NT, 0>(D, it, args, w, lds, red);
 }
 
 // rho[g] = sum_chunks dpart[c][g][0];  j[g][d] = sum_chunks dpart[c][g][1 + d] + A_d rho.
