@@ -117,7 +117,9 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
-  if (is_split(prec)) return d.n_proj >= 96 ? 0 : 1;
+  // FP16: the 32-deep LDS stage (variant 2) fits two waves per SIMD; the BF16
+  // build of it needs more registers and runs at one
+  if (is_split(prec)) return d.n_proj >= 96 ? (prec == DCMESH_SPLIT_FP16 ? 2 : 0) : 1;
   const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
   return bigm ? (bign ? 0 : 1) : (bign ? 2 : 1);
 }

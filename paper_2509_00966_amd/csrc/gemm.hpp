@@ -354,6 +354,9 @@ __global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ 
     }
     __syncthreads();
   }
+  // out += acc: every read is issued before the first write, so the reads
+  // overlap instead of each waiting behind the previous write
+  TIn prev[TM][TN][4];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -362,10 +365,17 @@ __global__ __launch_bounds__(kBlock) void k_correct(const DomDesc* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         const long long g = g0 + wm0 + i * 16 + Mfma<TC>::row(lk, r);
         const int jj = j0 + wn0 + j * 16 + ll;
-        if (g < D.n_grid && jj < no2) {
-          TIn* o = out + g * no2 + jj;
-          *o = (TIn)((TC)*o + acc[i][j][r]);
-        }
+        prev[i][j][r] = (g < D.n_grid && jj < no2) ? out[g * no2 + jj] : (TIn)0;
+      }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + Mfma<TC>::row(lk, r);
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && jj < no2) out[g * no2 + jj] = (TIn)((TC)prev[i][j][r] + acc[i][j][r]);
       }
 }
 
@@ -610,20 +620,33 @@ __global__ __launch_bounds__(kBlock) void k_correct3m(const DomDesc* __restrict_
     }
     __syncthreads();
   }
+  // out += result, one 16-row tile at a time: the tile's reads are all issued
+  // before its first write, so they overlap instead of each waiting behind the
+  // previous write (a whole-block batch would cost the registers of a second
+  // wave per SIMD)
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    float2 prev[TN][4];
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
         const int n = n0 + wn0 + j * 16 + ll;
-        if (g < D.n_grid && n < no) {
-          float2* o = reinterpret_cast<float2*>(out + (g * no + n) * 2);
-          const float2 prev = *o;
-          *o = make_float2(prev.x + (k1[i][j][r] - k3[i][j][r]), prev.y + (k1[i][j][r] + k2[i][j][r]));
-        }
+        prev[j][r] = (g < D.n_grid && n < no) ? *reinterpret_cast<const float2*>(out + (g * no + n) * 2)
+                                               : make_float2(0.f, 0.f);
       }
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int n = n0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && n < no)
+          *reinterpret_cast<float2*>(out + (g * no + n) * 2) =
+              make_float2(prev[j][r].x + (k1[i][j][r] - k3[i][j][r]), prev[j][r].y + (k1[i][j][r] + k2[i][j][r]));
+      }
+  }
 }
 
 }  // namespace dcm

@@ -423,6 +423,9 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
   }
   const float unscale = MODE == 1 ? 1.0f / (fp16_scale_from_bits(D.maxbits[0]) * fp16_scale_from_bits(D.maxbits[2]))
                                   : 1.0f;
+  // out += acc: every read is issued before the first write, so the reads
+  // overlap instead of each waiting behind the previous write
+  float prev[TM][TN][4];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -431,7 +434,17 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
       for (int r = 0; r < 4; ++r) {
         const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
         const int jj = j0 + wn0 + j * 16 + ll;
-        if (g < D.n_grid && jj < no2) out[g * no2 + jj] += acc[i][j][r] * unscale;
+        prev[i][j][r] = (g < D.n_grid && jj < no2) ? out[g * no2 + jj] : 0.f;
+      }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && jj < no2) out[g * no2 + jj] = prev[i][j][r] + acc[i][j][r] * unscale;
       }
 }
 
