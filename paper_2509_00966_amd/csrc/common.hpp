@@ -129,6 +129,32 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// x as read from another lane of the same 16-lane row (DPP lane selection
+// CTRL), for any 4-byte-multiple type.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_mov(T x) {
+  static_assert(sizeof(T) % 4 == 0, "DPP moves 32-bit words");
+  struct Words { int w[sizeof(T) / 4]; };
+  Words a = __builtin_bit_cast(Words, x);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) a.w[i] = __builtin_amdgcn_mov_dpp(a.w[i], CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(T, a);
+}
+
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16), valid in every
+// lane of the group: swaps within pairs and quads, then the mirrored half of
+// each 8 and of each 16 lanes.  Lane 0 of a group adds in the same order as
+// the xor butterfly (v0 + v1) + (v2 + v3) + ..., with no LDS traffic.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
+  if constexpr (G >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  if constexpr (G >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  if constexpr (G >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+  if constexpr (G >= 16) v += dpp_mov<0x140>(v);  // row_mirror
+  return v;
+}
+
 // Sum over a block of NW waves (lds holds NW values); result valid in
 // thread 0, added in wave order.
 template <typename T, int NW = kBlock / kWave>

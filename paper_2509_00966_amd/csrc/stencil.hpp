@@ -17,7 +17,7 @@
 // With want_density the sweep also produces, per (grid point, orbital chunk),
 // the partial sums sum_n f_n |u_n|^2 and sum_n f_n Im(conj(u_n) D1_d u_n) of
 // the density and the paramagnetic current (reduced over the chunk's lanes
-// with shuffles); k_density_finish adds the chunks in order.
+// with DPP row operations); k_density_finish adds the chunks in order.
 #pragma once
 
 #include <utility>
@@ -223,9 +223,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep(const DomDesc* __restrict_
         T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
                    fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+        for (int i = 0; i < 4; ++i) dv[i] = group_sum<OC>(dv[i]);
         const int x = x0 + lxk[k], y = y0 + lyk[k];
         if (o == 0 && x < nx && y < ny) {
           const long long g = (long long)z * plane + gcol[k];
@@ -396,9 +394,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep2(const DomDesc* __restrict
         T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
                    fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+        for (int i = 0; i < 4; ++i) dv[i] = group_sum<OC>(dv[i]);
         const int x = x0 + lxk[k], y = y0 + lyk[k];
         if (o == 0 && x < nx && y < ny) {
           const long long g = (long long)z * plane + gcol[k];
@@ -586,9 +582,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep3(const DomDesc* __restrict
         T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
                    fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+        for (int i = 0; i < 4; ++i) dv[i] = group_sum<OC>(dv[i]);
         const int x = x0 + lxk[k], y = y0 + lyk[k];
         if (o == 0 && x < nx && y < ny) {
           const long long g = (long long)z * plane + (long long)(cv[k] / sizeof(T));
@@ -774,9 +768,7 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
           T dv[4] = {fn * (c0.re * c0.re + c0.im * c0.im), fn * (c0.re * G[0].im - c0.im * G[0].re),
                      fn * (c0.re * G[1].im - c0.im * G[1].re), fn * (c0.re * G[2].im - c0.im * G[2].re)};
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int off = 1; off < OC; off <<= 1) dv[i] += __shfl_xor(dv[i], off, kWave);
+          for (int i = 0; i < 4; ++i) dv[i] = group_sum<OC>(dv[i]);
           const int col = tc + k * Cfg::kThrCols;
           const int x = x0 + col % TX, y = y0 + col / TX;
           if (o == 0 && x < nx && y < ny) {
