@@ -216,6 +216,29 @@ def make_domain(seed, shape: Sequence[int], n_orb: int, n_atoms: int,
                   d, occ, atoms)
 
 
+def projector_moments(dom: Domain) -> np.ndarray:
+    """Position-weighted projectors B_d[g, p] = (r_g - R_a)_d B[g, p], d = x, y, z,
+    where r_g - R_a is the minimum-image displacement of grid point g from the
+    atom a that projector column p belongs to (columns are atom-major, the same
+    number per atom).  [3, N_g, N_p] complex128."""
+    n_proj, n_atoms = dom.proj.shape[1], len(dom.atoms)
+    out = np.zeros((3, dom.n_grid, n_proj), dtype=np.complex128)
+    if n_proj == 0:
+        return out
+    per = n_proj // n_atoms
+    nx, ny, nz = dom.shape
+    L = np.array(dom.shape, dtype=np.float64) * dom.h
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = dom.h * np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    for a in range(n_atoms):
+        disp = r - dom.atoms[a]
+        disp -= L * np.round(disp / L)
+        cols = slice(a * per, (a + 1) * per)
+        for d in range(3):
+            out[d][:, cols] = disp[:, d:d + 1] * dom.proj[:, cols]
+    return out
+
+
 def pulse_midpoints(n_steps: int, dt: float, period_steps: int,
                     a0: float = PULSE_A0, omega: float = PULSE_OMEGA) -> np.ndarray:
     """A(t_k + dt/2) for A_z(t) = a0 sin(omega t) sin^2(pi t / T), T = period_steps*dt."""
