@@ -129,8 +129,8 @@ typedef struct dcmesh_density_out {
   double* overlap;
 } dcmesh_density_out;
 
-/* Workspace needed by dcmesh_step, dcmesh_density, dcmesh_occupations and
- * dcmesh_adjoint_step for these domains and precision (one size serves all).  Host-only; writes
+/* Workspace needed by every entry point below (one size serves all, except
+ * dcmesh_step_eq2: DCMESH_FLAG_EQ2) for these domains and precision.  Host-only; writes
  * *bytes.  Workspace pointers must be 256-byte aligned. */
 int dcmesh_workspace_bytes(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
                            uint32_t flags, size_t* bytes);
@@ -190,6 +190,45 @@ int dcmesh_occupations(const dcmesh_domain* doms, int32_t n_dom, int32_t precisi
                        const void* const* psi0, double* const* overlap,
                        double* const* f_out, double* n_exc,
                        void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* Macroscopic particle current density of each domain (the current that the
+ * Maxwell equations for the field take, Sec. V.B.5: its nonlocal correction is
+ * formed with projector products):
+ *     J = (h^3 sum_g j(g) + J_nl) / Omega,   Omega = N_g h^3,
+ *     j(g) = sum_n f_n [Im(conj psi_n D1 psi_n) + A |psi_n|^2]   (as dcmesh_density)
+ *     J_nl,d = sum_n f_n <psi_n| i[V_nl, r_d] |psi_n>
+ *            = -2 sum_{n,p} f_n D_p Im(conj(P_pn) R_d,pn),
+ *     P = h^3 B^H Psi,  R_d = h^3 B_d^H Psi,
+ * with B_d = (r - R_atom)_d B the position-weighted projectors, r measured from
+ * each projector's atom (any per-projector origin gives the same commutator).
+ *   a_dev    device float64 [n_a][3], the field of the state (n_a = n_dom or 1)
+ *   proj_r   NULL (no nonlocal part), or host array [n_dom] of device pointers to
+ *            [3][N_g][n_proj] complex in the precision's storage type; entries
+ *            may be NULL only for domains without projectors
+ *   current  device float64 [n_dom][3] output
+ * FP64 and FP32.  Workspace as dcmesh_step.  Deterministic. */
+int dcmesh_current(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                   const double* a_dev, int32_t a_per_domain, const void* const* proj_r,
+                   double* current, void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* n_steps Taylor-4 steps coupled to the Maxwell equation of a uniform vector
+ * potential: the field is A = A_ext + A_ind with d^2 A_ind / dt^2 = -4 pi J
+ * (J the macroscopic particle current density of dcmesh_current, atomic units,
+ * e/c folded into A).  Per step k, with A_ind at the step times and its rate b
+ * at the half steps:
+ *     J_k = J(psi_k, A_ext(t_k) + A_ind);  b -= 4 pi dt J_k;  A_ind' = A_ind + dt b
+ *     psi_k+1 = T4(-i dt H(A_mid)) psi_k,
+ *     A_mid = (A_ext(t_k) + A_ext(t_k+1)) / 2 + (A_ind + A_ind') / 2.
+ *   a_ext    device float64 [n_a][n_steps + 1][3] at the step times
+ *   field    device float64 [n_dom][6] in/out: A_ind (3), then b (3)
+ *   a_mid    device float64 [n_dom][n_steps][3] output: the step fields
+ *   current  NULL or device float64 [n_dom][n_steps][3] output: J_k
+ *   proj_r   as dcmesh_current (NULL: local current only)
+ * FP64 and FP32.  Workspace as dcmesh_step.  No host synchronisation. */
+int dcmesh_step_maxwell(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                        const void* const* proj_r, const double* a_ext, int32_t a_per_domain,
+                        double dt, int32_t n_steps, double* field, double* a_mid, double* current,
+                        void* work, size_t work_bytes, uint32_t flags, void* stream);
 
 /* One step of the adjoint recursion for the gradient of a loss L(psi_N):
  *     lambda_k = U_k^H lambda_{k+1} = T4(+i dt H(A_k)) lambda_{k+1}

@@ -9,6 +9,7 @@ from .api import (  # noqa: F401
     Workspace,
     adjoint_step,
     complex_dtype,
+    current,
     density,
     occupations,
     profile_collect,
@@ -16,6 +17,7 @@ from .api import (  # noqa: F401
     set_tuning,
     step,
     step_eq2,
+    step_maxwell,
     tuning_options,
     workspace_bytes,
 )

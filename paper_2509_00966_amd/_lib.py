@@ -26,7 +26,7 @@ KERNEL = {"stencil": 0, "project": 1, "correct": 2, "zseg": 3}
 
 EXPORTS = (
     "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_step_eq2", "dcmesh_density", "dcmesh_occupations",
-    "dcmesh_adjoint_step",
+    "dcmesh_current", "dcmesh_step_maxwell", "dcmesh_adjoint_step",
     "dcmesh_graph_create", "dcmesh_graph_launch", "dcmesh_graph_destroy",
     "dcmesh_set_tuning", "dcmesh_tuning_options", "dcmesh_profile_collect", "dcmesh_last_error",
 )
@@ -71,6 +71,8 @@ def _load():
         "dcmesh_step_eq2": [dom_p, I32, I32, ctypes.POINTER(P), D, P, I32, I64, D, I32, P, SZ, U32, P],
         "dcmesh_occupations": [dom_p, I32, I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,
                                P, SZ, U32, P],
+        "dcmesh_current": [dom_p, I32, I32, P, I32, ctypes.POINTER(P), P, P, SZ, U32, P],
+        "dcmesh_step_maxwell": [dom_p, I32, I32, ctypes.POINTER(P), P, I32, D, I32, P, P, P, P, SZ, U32, P],
         "dcmesh_adjoint_step": [dom_p, I32, I32, ctypes.POINTER(P), P, I32, D, P, P, SZ, U32, P],
         "dcmesh_graph_create": [dom_p, I32, I32, P, I32, I64, D, I32, ctypes.POINTER(DcmeshObs), P, SZ, U32, P,
                                 ctypes.POINTER(P)],

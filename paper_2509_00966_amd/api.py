@@ -197,6 +197,53 @@ def occupations(domains: Sequence[Domain], psi0: Sequence[torch.Tensor], precisi
     return f, n_exc
 
 
+def _proj_r(proj_r, domains, precision):
+    if proj_r is None:
+        return None
+    if len(proj_r) != len(domains):
+        raise ValueError("one proj_r per domain")
+    cd = _CPLX[precision]
+    for b, d in zip(proj_r, domains):
+        if b is None:
+            continue
+        if b.dtype != cd or tuple(b.shape) != (3,) + tuple(d.proj.shape) or not b.is_contiguous():
+            raise ValueError("proj_r entries are contiguous [3, N_g, N_p] in the orbitals' complex dtype")
+    return (ctypes.c_void_p * len(domains))(*[_ptr(b) for b in proj_r])
+
+
+def current(domains: Sequence[Domain], a: torch.Tensor, precision: str, work: Workspace, proj_r=None,
+            a_per_domain: bool = False, stream=None) -> torch.Tensor:
+    """Macroscopic particle current density [n_dom, 3] (float64) of the current
+    orbitals in the field ``a`` ([3] or [n_dom, 3], float64 device)."""
+    arr = _doms(domains, precision)
+    out = torch.empty(len(domains), 3, dtype=torch.float64, device=domains[0].psi.device)
+    check(lib.dcmesh_current(arr, len(domains), PRECISION[precision], a.data_ptr(), int(a_per_domain),
+                             _proj_r(proj_r, domains, precision), out.data_ptr(), work.ptr, work.nbytes, 0,
+                             _stream(stream)))
+    return out
+
+
+def step_maxwell(domains: Sequence[Domain], a_ext: torch.Tensor, dt: float, n_steps: int, precision: str,
+                 work: Workspace, field: torch.Tensor, proj_r=None, want_current: bool = False,
+                 a_per_domain: bool = False, stream=None):
+    """n_steps steps coupled to the Maxwell update of the field.  a_ext:
+    float64 [n_steps + 1, 3] (or [n_dom, n_steps + 1, 3]) at the step times;
+    field: float64 [n_dom, 6] (induced field, its rate), updated in place.
+    Returns (step fields [n_dom, n_steps, 3], currents [n_dom, n_steps, 3] or None)."""
+    arr = _doms(domains, precision)
+    dev = domains[0].psi.device
+    if field.dtype != torch.float64 or tuple(field.shape) != (len(domains), 6) or not field.is_contiguous():
+        raise ValueError("field is contiguous float64 [n_dom, 6]")
+    if a_ext.shape[-2] != n_steps + 1:
+        raise ValueError("a_ext holds n_steps + 1 samples")
+    a_mid = torch.empty(len(domains), max(n_steps, 1), 3, dtype=torch.float64, device=dev)
+    cur = torch.empty_like(a_mid) if want_current else None
+    check(lib.dcmesh_step_maxwell(arr, len(domains), PRECISION[precision], _proj_r(proj_r, domains, precision),
+                                  a_ext.data_ptr(), int(a_per_domain), float(dt), int(n_steps), field.data_ptr(),
+                                  a_mid.data_ptr(), _ptr(cur), work.ptr, work.nbytes, 0, _stream(stream)))
+    return a_mid[:, :n_steps], (cur[:, :n_steps] if cur is not None else None)
+
+
 def adjoint_step(domains: Sequence[Domain], lambdas: Sequence[torch.Tensor], a: torch.Tensor, dt: float,
                  grad: torch.Tensor, precision: str, work: Workspace, a_per_domain: bool = False, stream=None):
     """lambda <- U^H lambda in place; grad (float64 device, [3] or [n_dom, 3]) += dL/dA."""

@@ -87,6 +87,17 @@ struct DomDesc {
   DCM_GLOBAL double* f_occ;                // [n_orb] occupations of the reference orbitals
   DCM_GLOBAL double* n_exc;                // one value: electrons outside the reference span
   int item0_occ;                // first item of this domain in its occupation-row launch
+  // macroscopic current and the Maxwell update of the field
+  const DCM_GLOBAL void* proj_r;   // [3][N_g][n_proj] complex position-weighted projectors (or null)
+  const DCM_GLOBAL double* a_ext;  // [n_steps + 1][3] external field at the step times (Maxwell steps)
+  DCM_GLOBAL double* jpart;        // [n_dens_items][4] block sums of rho and the paramagnetic current
+  DCM_GLOBAL double* jnl_part;     // [3][n_e_nl] block sums of the nonlocal current
+  DCM_GLOBAL double* cur;          // [3] macroscopic current density
+  DCM_GLOBAL double* cur_out;      // [n_steps][3] per-step currents (Maxwell steps, or null)
+  DCM_GLOBAL double* field;        // [6] induced field and its rate (Maxwell steps)
+  DCM_GLOBAL double* amid;         // [n_steps][3] step fields written by the Maxwell update
+  int item0_dens;                  // first item of this domain in its density launch
+  int n_dens;                      // density items of this domain
   // split-precision operands (16-bit hi and lo planes), null otherwise
   DCM_GLOBAL void* bs_hi; DCM_GLOBAL void* bs_lo;    // [N_g][ldbs]       projectors as stored
   DCM_GLOBAL void* bt_hi; DCM_GLOBAL void* bt_lo;    // [n_proj][ldbt]    projectors transposed
@@ -153,6 +164,16 @@ __device__ __forceinline__ T group_sum(T v) {
   if constexpr (G >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
   if constexpr (G >= 16) v += dpp_mov<0x140>(v);  // row_mirror
   return v;
+}
+
+// Left operand of a projection: a psi-sized slot (a_slot >= 0), the
+// projectors B (-1), or component d of the position-weighted projectors
+// B_d = (r - R_atom)_d B (-2 - d).  ES: bytes of one real element.
+template <int ES>
+__device__ __forceinline__ const DCM_GLOBAL char* proj_operand(const DomDesc& D, int a_slot) {
+  if (a_slot >= 0) return (const DCM_GLOBAL char*)D.slot[a_slot];
+  if (a_slot == -1) return (const DCM_GLOBAL char*)D.proj;
+  return (const DCM_GLOBAL char*)D.proj_r + (long long)(-2 - a_slot) * D.n_grid * D.n_proj * 2 * ES;
 }
 
 // Sum over a block of NW waves (lds holds NW values); result valid in

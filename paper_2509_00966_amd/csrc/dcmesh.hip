@@ -327,9 +327,13 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     for (long long gt = 0; gt < cdiv(D.n_grid, t.bm); ++gt)
       for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, (int)gt, nt, 0});
   });
-  group_launch(P.dens, P.items, n_dom, [](int) { return 0; }, [&](int i, std::vector<Item>& it) {
-    for (long long b = 0; b < cdiv(P.desc[i].n_grid, 4); ++b) it.push_back({i, (int)b, 0, 0});
-  });
+  group_launch(P.dens, P.items, n_dom, [](int) { return 0; },
+               [&](int i, std::vector<Item>& it) {
+                 DomDesc& D = P.desc[i];
+                 D.n_dens = (int)cdiv(D.n_grid, 4);
+                 for (long long b = 0; b < D.n_dens; ++b) it.push_back({i, (int)b, 0, 0});
+               },
+               [&](int i, int first) { P.desc[i].item0_dens = first; });
   group_launch(P.elem, P.items, n_dom, [](int) { return 0; },
                [&](int i, std::vector<Item>& it) {
                  const DomDesc& D = P.desc[i];
@@ -442,6 +446,9 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.cn_part = as_global((double*)take(sizeof(double) * (size_t)D.n_rows_blocks * D.n_orb));
     D.cn_inv = as_global((double*)take(sizeof(double) * D.n_orb));
     D.smat = as_global((double*)take(16 * (size_t)D.n_orb * D.n_orb));
+    D.jpart = as_global((double*)take(4 * sizeof(double) * (size_t)std::max(1, D.n_dens)));
+    D.jnl_part = as_global((double*)take(3 * sizeof(double) * (size_t)std::max(1, D.n_e_nl)));
+    D.cur = as_global((double*)take(3 * sizeof(double)));
     if (is_split(prec) && D.n_proj > 0) {
       const size_t nbs = (size_t)D.n_grid * D.ldbs * 2, nbt = (size_t)D.n_proj * D.ldbt * 2;   // 16-bit values
       D.bs_hi = as_global(take(nbs)); D.bs_lo = as_global(take(nbs));
@@ -656,9 +663,9 @@ void launch_stencil(const Ctx& c, const StencilArgs& a) {
 }
 
 template <typename T>
-void launch_project(const Ctx& c, int u_slot) {
+void launch_project(const Ctx& c, int u_slot, int a_slot = -1) {
   ProfScope prof_(DCMESH_FAM_PROJECT, c.s);
-  ProjArgs a{-1, u_slot, 0};
+  ProjArgs a{a_slot, u_slot, 0};
   for (const Launch& L : c.P->proj) {
     const Item* it = c.d_items + L.first;
     const dim3 g(L.count), b(kBlock);
@@ -857,6 +864,27 @@ void launch_overlap(const Ctx& c, int a_slot = SLOT_PSI) {
   for (const Launch& L : c.P->ovl_reduce) k_reduce<double><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, r);
 }
 
+// Macroscopic current of psi into D.cur: block sums of rho and the
+// paramagnetic current; with the position-weighted projectors, P = h^3 B^H psi
+// (left in D.pmat by the reduce) and the three products h^3 B_d^H psi reduced
+// against it; then the final sum.  step >= 0: the field is the Maxwell state's.
+template <typename T>
+void launch_current(const Ctx& c, int step, bool nonlocal) {
+  launch_density<T>(c, 0, 0);
+  if (nonlocal) {
+    launch_project<T>(c, SLOT_PSI);
+    launch_reduce<T>(c, 1.0, 0.0, 0, 0);
+    for (int d = 0; d < 3; ++d) {
+      launch_project<T>(c, SLOT_PSI, -2 - d);
+      ProfScope prof_(DCMESH_FAM_REDUCE, c.s);
+      for (const Launch& L : c.P->reduce) k_jnl_partial<T><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, d);
+    }
+  }
+  ProfScope prof_(DCMESH_FAM_DENSITY, c.s);
+  for (const Launch& L : c.P->energy)
+    k_current_final<<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first, step, nonlocal ? 1 : 0);
+}
+
 // f_s and n_exc from the cross overlap with the reference orbitals in
 // SLOT_LAMBDA.
 template <typename T>
@@ -929,18 +957,36 @@ int run_step_eq2(CallSetup& cs, int32_t n_steps, double dt, double v_nl) {
   return DCMESH_OK;
 }
 
+// One Taylor-4 step with the field sample k.
+template <typename T>
+void one_step(const Ctx& c, int k, double dt, bool want_rho_j, bool want_e) {
+  // stage 4 applies H to psi_k: it also yields E_k and the rho/j partials of psi_k
+  apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0, want_rho_j ? 1 : 0);
+  if (want_rho_j) launch_density_finish<T>(c, k, k);
+  apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, k, 0);
+  apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B0, 0.0, -dt / 2, 0, k, 0);
+  apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_PSI, 0.0, -dt, 0, k, 0);
+  if (want_e) launch_energy<T>(c, k);
+}
+
 template <typename T>
 int run_step(CallSetup& cs, int32_t n_steps, double dt, bool want_rho_j, bool want_e) {
   const Ctx& c = cs.c;
   if (is_split(c.P->prec) && c.P->any_proj && n_steps > 0) launch_presplit(c);
+  for (int k = 0; k < n_steps; ++k) one_step<T>(c, k, dt, want_rho_j, want_e);
+  return DCMESH_OK;
+}
+
+// n steps coupled to the Maxwell update: per step the current of psi_k in the
+// field A_ext(t_k) + A_ind, the leapfrog update (which writes the step field
+// into D.amid = D.a), then the Taylor step.
+template <typename T>
+int run_step_maxwell(CallSetup& cs, int32_t n_steps, double dt, bool nonlocal) {
+  const Ctx& c = cs.c;
   for (int k = 0; k < n_steps; ++k) {
-    // stage 4 applies H to psi_k: it also yields E_k and the rho/j partials of psi_k
-    apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0, want_rho_j ? 1 : 0);
-    if (want_rho_j) launch_density_finish<T>(c, k, k);
-    apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, k, 0);
-    apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B0, 0.0, -dt / 2, 0, k, 0);
-    apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_PSI, 0.0, -dt, 0, k, 0);
-    if (want_e) launch_energy<T>(c, k);
+    launch_current<T>(c, k, nonlocal);
+    for (const Launch& L : c.P->energy) k_field_update<<<L.count, 1, 0, c.s>>>(c.d_desc, c.d_items + L.first, k, dt);
+    one_step<T>(c, k, dt, false, false);
   }
   return DCMESH_OK;
 }
@@ -1122,6 +1168,7 @@ int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, 
       D.jcur = as_global(out[i].j);
       D.energy = as_global(out[i].energy);
       D.overlap = as_global(out[i].overlap);
+      D.jpart = nullptr;
     }
   });
   if (rc) return rc;
@@ -1165,6 +1212,87 @@ int dcmesh_occupations(const dcmesh_domain* doms, int32_t n_dom, int32_t precisi
   });
   if (rc) return rc;
   is_fp64(precision) ? launch_occupations<double>(cs.c) : launch_occupations<float>(cs.c);
+  return finish(cs, flags);
+}
+
+namespace {
+int check_proj_r(const dcmesh_domain* doms, int32_t n_dom, const void* const* proj_r) {
+  if (!proj_r) return DCMESH_OK;
+  for (int i = 0; i < n_dom; ++i)
+    if (doms[i].n_proj > 0 && !proj_r[i])
+      return fail(DCMESH_ERR_INVALID_ARGUMENT, "proj_r[" + std::to_string(i) + "] is NULL for a domain with projectors");
+  return DCMESH_OK;
+}
+}  // namespace
+
+int dcmesh_current(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const double* a_dev,
+                   int32_t a_per_domain, const void* const* proj_r, double* current, void* work,
+                   size_t work_bytes, uint32_t flags, void* stream) {
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  if (precision != DCMESH_FP64 && precision != DCMESH_FP32)
+    return fail(DCMESH_ERR_UNSUPPORTED, "dcmesh_current runs in FP64 or FP32");
+  if (!a_dev || !current) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_dev and current are required");
+  rc = check_proj_r(doms, n_dom, proj_r);
+  if (rc) return rc;
+  CallSetup cs;
+  hipStream_t s = (hipStream_t)stream;
+  rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
+    for (int i = 0; i < n_dom; ++i) {
+      DomDesc& D = P.desc[i];
+      D.slot[SLOT_PSI] = as_global(doms[i].psi);
+      D.v = as_global(doms[i].v_loc);
+      D.proj = as_global(doms[i].proj);
+      D.proj_r = proj_r ? as_global(proj_r[i]) : nullptr;
+      D.d = as_global(doms[i].d);
+      D.occ = as_global(doms[i].occ);
+      D.a = as_global(a_dev + (a_per_domain ? (long long)i * 3 : 0));
+      D.cur = as_global(current + (long long)i * 3);
+    }
+  });
+  if (rc) return rc;
+  const bool nl = proj_r != nullptr && cs.P.any_proj;
+  precision == DCMESH_FP64 ? launch_current<double>(cs.c, -1, nl) : launch_current<float>(cs.c, -1, nl);
+  return finish(cs, flags);
+}
+
+int dcmesh_step_maxwell(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const void* const* proj_r,
+                        const double* a_ext, int32_t a_per_domain, double dt, int32_t n_steps, double* field,
+                        double* a_mid, double* current, void* work, size_t work_bytes, uint32_t flags,
+                        void* stream) {
+  int rc = validate_domains(doms, n_dom, precision);
+  if (rc) return rc;
+  if (precision != DCMESH_FP64 && precision != DCMESH_FP32)
+    return fail(DCMESH_ERR_UNSUPPORTED, "dcmesh_step_maxwell runs in FP64 or FP32");
+  if (n_steps < 0) return fail(DCMESH_ERR_INVALID_ARGUMENT, "n_steps must be >= 0");
+  if (!a_ext || !field || !a_mid) return fail(DCMESH_ERR_INVALID_ARGUMENT, "a_ext, field and a_mid are required");
+  if (!std::isfinite(dt)) return fail(DCMESH_ERR_INVALID_ARGUMENT, "dt must be finite");
+  rc = check_proj_r(doms, n_dom, proj_r);
+  if (rc) return rc;
+  CallSetup cs;
+  hipStream_t s = (hipStream_t)stream;
+  rc = prepare(cs, doms, n_dom, precision, work, work_bytes, s, flags, [&](Plan& P) {
+    for (int i = 0; i < n_dom; ++i) {
+      DomDesc& D = P.desc[i];
+      D.slot[SLOT_PSI] = as_global(doms[i].psi);
+      D.v = as_global(doms[i].v_loc);
+      D.proj = as_global(doms[i].proj);
+      D.proj_r = proj_r ? as_global(proj_r[i]) : nullptr;
+      D.d = as_global(doms[i].d);
+      D.occ = as_global(doms[i].occ);
+      D.a_ext = as_global(a_ext + (a_per_domain ? (long long)i * (n_steps + 1) * 3 : 0));
+      D.amid = as_global(a_mid + (long long)i * n_steps * 3);
+      D.a = D.amid;
+      D.a_stride = 3;
+      D.field = as_global(field + (long long)i * 6);
+      D.cur_out = current ? as_global(current + (long long)i * n_steps * 3) : nullptr;
+    }
+  });
+  if (rc) return rc;
+  const bool nl = proj_r != nullptr && cs.P.any_proj;
+  rc = precision == DCMESH_FP64 ? run_step_maxwell<double>(cs, n_steps, dt, nl)
+                                : run_step_maxwell<float>(cs, n_steps, dt, nl);
+  if (rc) return rc;
   return finish(cs, flags);
 }
 

@@ -62,7 +62,7 @@ __device__ __forceinline__ Vec<T, VW> vzero() {
 }
 
 struct ProjArgs {
-  int a_slot;        // -1: the projectors B; else a psi-sized slot (overlap)
+  int a_slot;        // left operand (proj_operand): slot >= 0 (overlap), -1 B, -2 - d B_d
   int u_slot;        // right operand
   int out_overlap;   // unused by the kernel (kept for the launch record)
 };
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_project(const DomDesc* __restrict__ 
   const DomDesc& D = doms[it.dom];
   const int np = args.a_slot < 0 ? D.n_proj : D.n_orb;
   const int no2 = 2 * D.n_orb;
-  const TIn* __restrict__ Bsrc = args.a_slot < 0 ? (const TIn*)D.proj : (const TIn*)D.slot[args.a_slot];
+  const TIn* __restrict__ Bsrc = (const TIn*)proj_operand<sizeof(TIn)>(D, args.a_slot);
   const TIn* __restrict__ U = (const TIn*)D.slot[args.u_slot];
   const int p0 = it.a * BM, j0 = it.b * BN;
   const long long g_begin = (long long)it.c * D.split_len;
@@ -258,6 +258,38 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
   }
 }
 
+// Nonlocal current of one axis d: with P = h^3 B^H u in D.pmat (left by
+// k_reduce) and the split-K partials of h^3 B_d^H u in D.ppart, the block sums
+// of f_n D_p Im(conj(P_pn) R_pn), R summed over the splits in order, go to
+// jnl_part[d][item].  Items: those of k_reduce.
+template <typename TC>
+__global__ __launch_bounds__(kBlock) void k_jnl_partial(const DomDesc* __restrict__ doms,
+                                                        const Item* __restrict__ items, int d) {
+  __shared__ double red[kBlock / kWave];
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no = D.n_orb, no2 = 2 * no;
+  const long long idx = (long long)it.a * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (idx < (long long)np * no) {
+    const int p = (int)(idx / no), n = (int)(idx % no);
+    const TC* part = (const TC*)D.ppart;
+    const long long stride = (long long)np * no2;
+    TC sr = 0, si = 0;
+    for (int s = 0; s < D.n_split; ++s) {
+      sr += part[s * stride + (long long)p * no2 + 2 * n];
+      si += part[s * stride + (long long)p * no2 + 2 * n + 1];
+    }
+    const double h3 = D.h * D.h * D.h;
+    const double rr = h3 * (double)sr, ri = h3 * (double)si;
+    const TC* P = (const TC*)D.pmat;
+    const double pr = (double)P[(long long)p * no2 + 2 * n], pi = (double)P[(long long)p * no2 + 2 * n + 1];
+    v = (double)((const TC*)D.occ)[n] * (double)((const TC*)D.d)[p] * (pr * ri - pi * rr);
+  }
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) D.jnl_part[(long long)d * D.n_e_nl + (blockIdx.x - D.item0_reduce)] = v;
+}
+
 // Items: (dom, g tile, j tile).  out_raw[g][j] += sum_k B_raw[g][k] Q'[k][j].
 // Block = 4 waves in 2 x 2; KC real reduction indices per LDS stage.  VW: load
 // width for the rows of B (2 n_proj must be a multiple of VW); Q' rows are
@@ -410,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_project3m(const DomDesc* __restrict_
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
   const int np = D.n_proj, no = D.n_orb, no2 = 2 * no;
-  const float* __restrict__ Bsrc = (const float*)D.proj;
+  const float* __restrict__ Bsrc = (const float*)proj_operand<4>(D, args.a_slot);
   const float* __restrict__ U = (const float*)D.slot[args.u_slot];
   const int p0 = it.a * BM, n0 = it.b * BNC;
   const long long g_begin = (long long)it.c * D.split_len;

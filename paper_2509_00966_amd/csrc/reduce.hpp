@@ -16,10 +16,11 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_density(const DomDesc* __restrict__ doms,
                                                     const Item* __restrict__ items, int step, int obs) {
   using C = Cplx<T>;
+  __shared__ double red[kBlock / kWave];
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
   const long long g = (long long)it.a * 4 + threadIdx.x / kWave;
-  if (g >= D.n_grid) return;
+  const bool valid = g < D.n_grid;
   const int lane = threadIdx.x % kWave;
   const int nx = D.nx, ny = D.ny, nz = D.nz, no = D.n_orb, r = D.r;
   const int x = (int)(g % nx), y = (int)((g / nx) % ny), z = (int)(g / ((long long)nx * ny));
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_density(const DomDesc* __restrict__ 
   const T* __restrict__ occ = (const T*)D.occ;
   const double ih = 1.0 / D.h;
   double rho = 0, j0 = 0, j1 = 0, j2 = 0;
-  for (int n = lane; n < no; n += kWave) {
+  for (int n = lane; valid && n < no; n += kWave) {
     const double f = (double)occ[n];
     const C c = psi[g * no + n];
     rho += f * ((double)c.re * c.re + (double)c.im * c.im);
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_density(const DomDesc* __restrict__ 
   j0 = wave_sum(j0);
   j1 = wave_sum(j1);
   j2 = wave_sum(j2);
-  if (lane == 0) {
+  if (lane == 0 && valid) {
     const double* A = D.a + (long long)step * D.a_stride;
     if (D.rho) ((T*)D.rho)[(long long)obs * D.n_grid + g] = (T)rho;
     if (D.jcur) {
@@ -65,6 +66,19 @@ __global__ __launch_bounds__(kBlock) void k_density(const DomDesc* __restrict__ 
       j[0] = (T)(j0 + A[0] * rho);
       j[1] = (T)(j1 + A[1] * rho);
       j[2] = (T)(j2 + A[2] * rho);
+    }
+  }
+  if (D.jpart) {
+    // block sums (four grid points, fixed order) of rho and the paramagnetic
+    // current for the macroscopic current
+    double* out = D.jpart + (long long)(blockIdx.x - D.item0_dens) * 4;
+    const double v[4] = {rho, j0, j1, j2};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (lane == 0) red[threadIdx.x / kWave] = v[i];
+      __syncthreads();
+      if (threadIdx.x == 0) out[i] = (red[0] + red[1]) + (red[2] + red[3]);
+      __syncthreads();
     }
   }
 }
@@ -297,6 +311,60 @@ __global__ __launch_bounds__(kBlock) void k_occ_final(const DomDesc* __restrict_
   }
   t = block_sum(t, red);
   if (threadIdx.x == 0) D.n_exc[0] = t;
+}
+
+// Macroscopic current density of a domain,
+//   J = (h^3 sum_g [j_para(g) + A rho(g)] - 2 sum f D Im(conj(P) R)) / Omega,
+// from the block sums of k_density and k_jnl_partial (summed in a fixed order).
+// A: the field of the state, D.a_ext[step] + field[0..2] for a Maxwell step
+// (step >= 0), else D.a.  Items: one per domain.
+__global__ __launch_bounds__(kBlock) void k_current_final(const DomDesc* __restrict__ doms,
+                                                          const Item* __restrict__ items, int step, int nonlocal) {
+  __shared__ double red[kBlock / kWave];
+  const DomDesc& D = doms[items[blockIdx.x].dom];
+  double s[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) s[i] = 0.0;
+  for (int b = threadIdx.x; b < D.n_dens; b += kBlock)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] += D.jpart[(long long)b * 4 + i];
+  if (nonlocal)
+    for (int b = threadIdx.x; b < D.n_e_nl; b += kBlock)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s[4 + d] += D.jnl_part[(long long)d * D.n_e_nl + b];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) s[i] = block_sum(s[i], red);
+  if (threadIdx.x == 0) {
+    double A[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) A[d] = step >= 0 ? D.a_ext[(long long)step * 3 + d] + D.field[d] : D.a[d];
+    const double h3 = D.h * D.h * D.h, vol = (double)D.n_grid * h3;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) D.cur[d] = (h3 * (s[1 + d] + A[d] * s[0]) - 2.0 * s[4 + d]) / vol;
+  }
+}
+
+// Leapfrog update of the induced field of a uniform vector potential driven by
+// the macroscopic particle current J_k (in D.cur):
+//   b <- b - 4 pi dt J_k,  A_ind' = A_ind + dt b,
+//   step field = (A_ext[k] + A_ext[k + 1]) / 2 + (A_ind + A_ind') / 2.
+// One thread per domain (items: one per domain).
+__global__ void k_field_update(const DomDesc* __restrict__ doms, const Item* __restrict__ items, int step,
+                               double dt) {
+  const DomDesc& D = doms[items[blockIdx.x].dom];
+  if (threadIdx.x != 0) return;
+  const double pi4 = 4.0 * 3.14159265358979323846;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double j = D.cur[d];
+    const double b = D.field[3 + d] - pi4 * dt * j;
+    const double a0 = D.field[d], a1 = a0 + dt * b;
+    D.amid[(long long)step * 3 + d] =
+        0.5 * (D.a_ext[(long long)step * 3 + d] + D.a_ext[(long long)(step + 1) * 3 + d]) + 0.5 * (a0 + a1);
+    D.field[d] = a1;
+    D.field[3 + d] = b;
+    if (D.cur_out) D.cur_out[(long long)step * 3 + d] = j;
+  }
 }
 
 }  // namespace dcm
