@@ -81,7 +81,8 @@ struct GemmVariant { int bm, bn; };
 // in complex orbitals is half the real-column tile listed here.
 const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
-constexpr int kNProj = 4;
+constexpr int kNProj = 5;      // FP32 variant 4: the three-product kernel with direct LDS loads
+constexpr int kProjDirect = 8; // its launch key
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 // split-precision kernels (variant 2 of each stages twice as much per LDS pass)
 const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}};
@@ -111,7 +112,18 @@ int wide_corr(const dcmesh_domain& d, int prec) {
 }
 int proj_variant_base(const dcmesh_domain& d, int prec);
 int corr_variant_base(const dcmesh_domain& d, int prec);
-int proj_variant(const dcmesh_domain& d, int prec) { return proj_variant_base(d, prec) + wide_proj(d, prec); }
+// The direct-LDS projection moves 16-byte chunks of whole rows (even n_proj
+// and n_orb) and addresses a split's rows with 32-bit byte offsets.
+bool direct_proj_ok(const dcmesh_domain& d, int prec) {
+  const long long rows = 2048;   // the longest split
+  return prec == DCMESH_FP32 && wide_proj(d, prec) && rows * 8 * d.n_proj < (1LL << 31) &&
+         rows * 8 * d.n_orb < (1LL << 31);
+}
+int proj_variant(const dcmesh_domain& d, int prec) {
+  const int base = proj_variant_base(d, prec);
+  if (base == 4) return direct_proj_ok(d, prec) ? kProjDirect : wide_proj(d, prec);
+  return base + wide_proj(d, prec);
+}
 int corr_variant(const dcmesh_domain& d, int prec) { return corr_variant_base(d, prec) + wide_corr(d, prec); }
 int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
@@ -121,7 +133,9 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   // build of it needs more registers and runs at one
   if (is_split(prec)) return d.n_proj >= 96 ? (prec == DCMESH_SPLIT_FP16 ? 2 : 0) : 1;
   const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
-  return bigm ? (bign ? 0 : 1) : (bign ? 2 : 1);
+  // large tiles: the three-product kernel with direct LDS loads where the rows
+  // allow it (proj_variant falls back to variant 0 otherwise)
+  return bigm ? (bign ? 4 : 1) : (bign ? 2 : 1);
 }
 int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
@@ -678,7 +692,8 @@ void launch_project(const Ctx& c, int u_slot, int a_slot = -1) {
         case 4: k_project3m<128, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 5: k_project<T, T, 64, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 6: k_project<T, T, 64, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
-        default: k_project<T, T, 128, 256, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 7: k_project<T, T, 128, 256, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        default: k_project3m_dl<128, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
       }
     } else {
       switch (L.variant) {

@@ -544,6 +544,132 @@ __global__ __launch_bounds__(kBlock) void k_project3m(const DomDesc* __restrict_
       }
 }
 
+// Raw buffer resource over [base, base + bytes): reads at or past the end
+// return zero (gfx9 descriptor word 3).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(const DCM_GLOBAL void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+}
+
+// 16 bytes per lane from a buffer into LDS: lane i's bytes land at
+// dst + 16 i (one wave moves 1 KB); dst is wave-uniform.
+__device__ __forceinline__ void load_lds16(__amdgpu_buffer_rsrc_t r, float* dst, unsigned voffset) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)dst, 16, voffset, 0, 0, 0);
+}
+
+// The three-product projection with the operand tiles moved from memory
+// straight into LDS (buffer loads with an LDS destination), double-buffered:
+// no staging registers and one barrier per stage.  A stage holds KG grid
+// points: KG rows of 2 BM floats of B (1 KB, one wave instruction each) and KG
+// rows of 2 BNC floats of u (512 B; one instruction moves two).  The buffers
+// start at the block's first grid point and end at its last, so rows past the
+// split read as zero; columns past n_proj or n_orb (read from the next row, or
+// zero) reach only outputs that are not stored.  Items as k_project3m.
+template <int BM, int BNC, int KG>
+__global__ __launch_bounds__(kBlock) void k_project3m_dl(const DomDesc* __restrict__ doms,
+                                                         const Item* __restrict__ items, ProjArgs args) {
+  constexpr int TM = BM / 32, TN = BNC / 32;
+  constexpr int RA = 2 * BM, RB = 2 * BNC;             // floats per LDS row
+  static_assert(RA == 256 && RB == 128, "rows of 1 KB (B) and 512 B (u)");
+  static_assert(KG % 8 == 0, "whole wave instructions per stage");
+  constexpr int SA = KG * RA, SB = KG * RB;
+  __shared__ __align__(16) float sA0[SA], sA1[SA];
+  __shared__ __align__(16) float sB0[SB], sB1[SB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no = D.n_orb, no2 = 2 * no;
+  const int p0 = it.a * BM, n0 = it.b * BNC;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+  const int n_st = (int)((g_end - g_begin + KG - 1) / KG);
+  const unsigned rowA = 8u * (unsigned)np, rowB = 8u * (unsigned)no;     // bytes per grid point
+  const DCM_GLOBAL char* Bsrc = proj_operand<4>(D, args.a_slot) + g_begin * rowA;
+  const DCM_GLOBAL char* Usrc = (const DCM_GLOBAL char*)D.slot[args.u_slot] + g_begin * rowB;
+  const __amdgpu_buffer_rsrc_t ra = buffer_over(Bsrc, (unsigned)(g_end - g_begin) * rowA);
+  const __amdgpu_buffer_rsrc_t rb = buffer_over(Usrc, (unsigned)(g_end - g_begin) * rowB);
+
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BNC / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  const unsigned colA = 4u * (2u * p0 + 4u * lane);              // this lane's 16 bytes of a B row
+  const unsigned colB = 4u * (2u * n0 + 4u * (lane % 32));       // ... of a u row
+  f32x4 k1[TM][TN], k2[TM][TN], k3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) k1[i][j] = k2[i][j] = k3[i][j] = f32x4{0, 0, 0, 0};
+
+  auto issue = [&](int st, float* sA, float* sB) {
+#pragma unroll
+    for (int r = wv; r < KG; r += 4) load_lds16(ra, sA + r * RA, (unsigned)(st * KG + r) * rowA + colA);
+#pragma unroll
+    for (int r2 = wv; r2 < KG / 2; r2 += 4)
+      load_lds16(rb, sB + 2 * r2 * RB, (unsigned)(st * KG + 2 * r2 + lane / 32) * rowB + colB);
+  };
+  auto compute = [&](const float* sA, const float* sB) {
+#pragma unroll 2
+    for (int ks = 0; ks < KG / 4; ++ks) {
+      const int gl = 4 * ks + lk;
+      float a1[TM], a2[TM], a3[TM], b1[TN], b2[TN], b3[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const float2 v = *reinterpret_cast<const float2*>(&sA[gl * RA + 2 * (wm0 + i * 16 + ll)]);
+        a1[i] = v.x - v.y;
+        a2[i] = v.x;
+        a3[i] = -v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const float2 v = *reinterpret_cast<const float2*>(&sB[gl * RB + 2 * (wn0 + j * 16 + ll)]);
+        b1[j] = v.x;
+        b2[j] = v.y - v.x;
+        b3[j] = v.x + v.y;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          k1[i][j] = Mfma<float>::run(a1[i], b1[j], k1[i][j]);
+          k2[i][j] = Mfma<float>::run(a2[i], b2[j], k2[i][j]);
+          k3[i][j] = Mfma<float>::run(a3[i], b3[j], k3[i][j]);
+        }
+    }
+  };
+  // stage st computes from buffer st % 2 while stage st + 1 streams into the
+  // other; the barrier after each wait makes a stage's rows visible to every
+  // wave and retires the readers of the buffer about to be refilled
+  if (n_st > 0) issue(0, sA0, sB0);
+  int st = 0;
+  for (; st + 1 < n_st; st += 2) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+    issue(st + 1, sA1, sB1);
+    compute(sA0, sB0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (st + 2 < n_st) issue(st + 2, sA0, sB0);
+    compute(sA1, sB1);
+  }
+  if (st < n_st) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    compute(sA0, sB0);
+  }
+  float* __restrict__ part = (float*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + wm0 + i * 16 + 4 * lk + r;
+        const int n = n0 + wn0 + j * 16 + ll;
+        if (p < np && n < no)
+          *reinterpret_cast<float2*>(&part[(long long)p * no2 + 2 * n]) =
+              make_float2(k1[i][j][r] - k3[i][j][r], k1[i][j][r] + k2[i][j][r]);
+      }
+}
+
 // Items: (dom, g tile, complex-orbital tile).  out[g][n] += sum_p B[g][p] Q[p][n]
 // with Q from the three planes D.qmat3 (rows of D.ldq3 floats).  Block = 4
 // waves in 2 x 2, wave tile (BMG/2) grid points x (BNC/2) orbitals; KC

@@ -314,6 +314,28 @@ def test_every_z_segment_choice_matches_oracle(api, zseg):
         assert rel_fro(_np(g.psi), ref) < TOL_PSI["fp32"], variant
 
 
+@pytest.mark.parametrize("shape,n_orb,n_atoms", [((19, 13, 21), 22, 3),     # N_g tail, 24 projectors
+                                                ((16, 16, 16), 64, 8),      # whole stages, 64 projectors
+                                                ((17, 15, 9), 21, 2)])      # odd N_o: falls back
+def test_direct_lds_projection_matches_oracle(api, shape, n_orb, n_atoms):
+    """The FP32 projection with operand tiles loaded straight into LDS (tuning
+    variant 4), two steps against the oracle."""
+    torch = _torch()
+    dom = make_domain(43, shape, n_orb, n_atoms, proj_per_atom=8, h=0.4, fd_order=6)
+    a_mid = _field(2)
+    od = oracle_inputs(dom, "fp32")
+    ref, _ = P.propagate(od, a_mid, 0.02, od.psi)
+    g = to_device(dom, "fp32")
+    ws = api.Workspace.for_domains([g], "fp32")
+    try:
+        api.set_tuning("project", 4)
+        api.step([g], a_tensor(a_mid), 0.02, 2, "fp32", ws)
+        torch.cuda.synchronize()
+    finally:
+        api.set_tuning("project", -1)
+    assert rel_fro(_np(g.psi), ref) < TOL_PSI["fp32"]
+
+
 def test_check_finite_flags_nan(api):
     torch = _torch()
     from paper_2509_00966_amd._lib import DcmeshError
