@@ -88,7 +88,7 @@ const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}};
 const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
-constexpr int kNCorr = 4;
+constexpr int kNCorr = 5;      // FP32 variant 4: the three-product kernel with the Q tile loaded into LDS directly
 constexpr int kProjKG = 16;
 
 std::atomic<int> g_tune[4] = {{-1}, {-1}, {-1}, {-1}};
@@ -124,7 +124,17 @@ int proj_variant(const dcmesh_domain& d, int prec) {
   if (base == 4) return direct_proj_ok(d, prec) ? kProjDirect : wide_proj(d, prec);
   return base + wide_proj(d, prec);
 }
-int corr_variant(const dcmesh_domain& d, int prec) { return corr_variant_base(d, prec) + wide_corr(d, prec); }
+// The direct-LDS correction (launch keys 8 and 12: 8-byte and 16-byte
+// loads of the projector rows) addresses each Q plane with 32-bit offsets.
+bool direct_corr_ok(const dcmesh_domain& d, int prec) {
+  const long long ldq3 = (d.n_orb + 3) / 4 * 4;
+  return prec == DCMESH_FP32 && (long long)d.n_proj * ldq3 * 4 < (1LL << 31);
+}
+int corr_variant(const dcmesh_domain& d, int prec) {
+  const int base = corr_variant_base(d, prec);
+  if (base == 4) return direct_corr_ok(d, prec) ? (wide_corr(d, prec) ? 12 : 8) : wide_corr(d, prec);
+  return base + wide_corr(d, prec);
+}
 int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
   if (t >= 0) return t;
@@ -143,7 +153,9 @@ int corr_variant_base(const dcmesh_domain& d, int prec) {
   if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
   if (is_split(prec)) return 2 * d.n_orb > 128 ? 0 : 1;
   const int n2 = 2 * d.n_orb;
-  return n2 > 128 ? 0 : (n2 > 64 ? 1 : 2);
+  // large tiles: the three-product kernel with the Q tile loaded into LDS
+  // directly (corr_variant falls back to variant 0 where it cannot run)
+  return n2 > 128 ? 4 : (n2 > 64 ? 1 : 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,7 +741,9 @@ void launch_correct(const Ctx& c, int out_slot) {
         case 4: k_correct3m<64, 128, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 5: k_correct<T, T, 64, 128, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 6: k_correct<T, T, 64, 64, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-        default: k_correct<T, T, 128, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 7: k_correct<T, T, 128, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 8: k_correct3m_dl<64, 128, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        default: k_correct3m_dl<64, 128, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       }
     } else {
       switch (L.variant) {

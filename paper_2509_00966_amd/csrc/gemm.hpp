@@ -588,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_project3m_dl(const DomDesc* __restri
   const __amdgpu_buffer_rsrc_t ra = buffer_over(Bsrc, (unsigned)(g_end - g_begin) * rowA);
   const __amdgpu_buffer_rsrc_t rb = buffer_over(Usrc, (unsigned)(g_end - g_begin) * rowB);
 
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BNC / 2);
   const int ll = lane % 16, lk = lane / 16;
   const unsigned colA = 4u * (2u * p0 + 4u * lane);              // this lane's 16 bytes of a B row
@@ -807,4 +807,174 @@ __global__ __launch_bounds__(kBlock) void k_correct3m(const DomDesc* __restrict_
   }
 }
 
+// The three-product correction with the Q tile moved from memory straight
+// into LDS (buffer loads with an LDS destination) and both tiles
+// double-buffered (one barrier per stage).  A stage holds KC projectors: the
+// three Q planes give 3 KC rows of BNC floats (512 B; one wave instruction
+// moves two rows), and the projector rows of B are staged through registers
+// into padded LDS rows as in k_correct3m.  Odd Q rows are stored rotated by 16
+// floats, so the two 16-lane halves that read consecutive rows use disjoint
+// LDS banks.  Each plane's buffer ends after n_proj rows, so rows past it read
+// as zero; columns past n_orb reach only outputs that are not stored.
+template <int BMG, int BNC, int KC, int VW>
+__global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restrict__ doms,
+                                                         const Item* __restrict__ items, int out_slot) {
+  constexpr int TM = BMG / 32, TN = BNC / 32;
+  constexpr int LA = 2 * KC + 2;
+  static_assert(BNC == 128, "Q rows of 512 B");
+  static_assert(KC % 2 == 0, "Q rows move in pairs");
+  constexpr int VA = BMG * 2 * KC / VW;
+  constexpr int RA = (VA + kBlock - 1) / kBlock;
+  constexpr int SB = 3 * KC * BNC;
+  __shared__ __align__(16) float sA0[BMG * LA], sA1[BMG * LA];
+  __shared__ __align__(16) float sB0[SB], sB1[SB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no = D.n_orb, K2 = 2 * np;
+  const long long ldq3 = D.ldq3;
+  const long long g0 = (long long)it.a * BMG;
+  const int n0 = it.b * BNC;
+  const float* __restrict__ Braw = (const float*)D.proj;
+  float* __restrict__ out = (float*)D.slot[out_slot];
+  const unsigned qrow = 4u * (unsigned)ldq3;                     // bytes per Q row
+  __amdgpu_buffer_rsrc_t rq[3];
+#pragma unroll
+  for (int pl = 0; pl < 3; ++pl)
+    rq[pl] = buffer_over((const DCM_GLOBAL char*)D.qmat3 + (long long)pl * np * qrow, (unsigned)np * qrow);
+
+  // the wave index is uniform: buffer descriptors and LDS destinations chosen
+  // by it stay in scalar registers
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = (wv / 2) * (BMG / 2), wn0 = (wv % 2) * (BNC / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  // lanes 0-31 move an even row, 32-63 the next (odd) row rotated by 16 floats
+  const int qt = lane % 32;
+  const unsigned qcol = 4u * (unsigned)(n0 + 4 * (lane < 32 ? qt : (qt + 4) % 32));
+  const int bshift = (lk & 1) ? 16 : 0;                          // this lane reads odd rows
+  f32x4 k1[TM][TN], k2[TM][TN], k3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) k1[i][j] = k2[i][j] = k3[i][j] = f32x4{0, 0, 0, 0};
+
+  Vec<float, VW> ra[RA];
+  auto load_a = [&](int st) {
+    const int p0 = st * KC;
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (2 * KC / VW), c = (idx % (2 * KC / VW)) * VW;
+      const long long g = g0 + r;
+      const int k = 2 * p0 + c;
+      ra[q] = (idx < VA && g < D.n_grid && k < K2) ? vload<float, VW>(Braw + g * K2 + k) : vzero<float, VW>();
+    }
+  };
+  auto store_a = [&](float* sA) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (2 * KC / VW), c = (idx % (2 * KC / VW)) * VW;
+#pragma unroll
+        for (int e = 0; e < VW; e += 2)
+          *reinterpret_cast<float2*>(&sA[r * LA + c + e]) = make_float2(ra[q].v[e], ra[q].v[e + 1]);
+      }
+    }
+  };
+  auto issue_q = [&](int st, float* sB) {
+    // row pairs (plane, 2m), (plane, 2m + 1): 3 KC / 2 instructions per stage
+#pragma unroll
+    for (int pr = wv; pr < 3 * KC / 2; pr += 4) {
+      const int pl = pr / (KC / 2), m = pr % (KC / 2);
+      const int row = st * KC + 2 * m + lane / 32;
+      load_lds16(rq[pl], sB + (pl * KC + 2 * m) * BNC, (unsigned)row * qrow + qcol);
+    }
+  };
+  auto compute = [&](const float* sA, const float* sB) {
+#pragma unroll 2
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int pl = 4 * ks + lk;
+      float a1[TM], a2[TM], a3[TM], b1[TN], b2[TN], b3[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const float2 v = *reinterpret_cast<const float2*>(&sA[(wm0 + i * 16 + ll) * LA + 2 * pl]);
+        a1[i] = v.x + v.y;
+        a2[i] = v.x;
+        a3[i] = v.y;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int pos = (wn0 + j * 16 + ll - bshift) & (BNC - 1);
+        b1[j] = sB[(0 * KC + pl) * BNC + pos];
+        b2[j] = sB[(1 * KC + pl) * BNC + pos];
+        b3[j] = sB[(2 * KC + pl) * BNC + pos];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          k1[i][j] = Mfma<float>::run(a1[i], b1[j], k1[i][j]);
+          k2[i][j] = Mfma<float>::run(a2[i], b2[j], k2[i][j]);
+          k3[i][j] = Mfma<float>::run(a3[i], b3[j], k3[i][j]);
+        }
+    }
+  };
+  // stage st reads buffer st % 2; the wait + barrier at its top publishes its
+  // tiles and retires the readers of the buffers about to be refilled
+  const int n_st = (np + KC - 1) / KC;
+  if (n_st > 0) {
+    load_a(0);
+    issue_q(0, sB0);
+  }
+  int st = 0;
+  for (; st + 1 < n_st; st += 2) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    store_a(sA0);
+    __syncthreads();
+    load_a(st + 1);
+    issue_q(st + 1, sB1);
+    compute(sA0, sB0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store_a(sA1);
+    __syncthreads();
+    if (st + 2 < n_st) {
+      load_a(st + 2);
+      issue_q(st + 2, sB0);
+    }
+    compute(sA1, sB1);
+  }
+  if (st < n_st) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store_a(sA0);
+    __syncthreads();
+    compute(sA0, sB0);
+  }
+  // out += result, one 16-row tile at a time (reads before writes)
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    float2 prev[TN][4];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int n = n0 + wn0 + j * 16 + ll;
+        prev[j][r] = (g < D.n_grid && n < no) ? *reinterpret_cast<const float2*>(out + (g * no + n) * 2)
+                                               : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int n = n0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && n < no)
+          *reinterpret_cast<float2*>(out + (g * no + n) * 2) =
+              make_float2(prev[j][r].x + (k1[i][j][r] - k3[i][j][r]), prev[j][r].y + (k1[i][j][r] + k2[i][j][r]));
+      }
+  }
+}
+
 }  // namespace dcm
+
