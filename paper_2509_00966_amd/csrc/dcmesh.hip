@@ -119,9 +119,18 @@ bool direct_proj_ok(const dcmesh_domain& d, int prec) {
   return prec == DCMESH_FP32 && wide_proj(d, prec) && rows * 8 * d.n_proj < (1LL << 31) &&
          rows * 8 * d.n_orb < (1LL << 31);
 }
+// The direct-LDS split projection addresses 128 rows of the transposed
+// projector planes (2 ldbt bytes each) with 32-bit offsets.
+bool direct_split_proj_ok(const dcmesh_domain& d) {
+  const long long ldbt = (2LL * d.nx * d.ny * d.nz + 7) / 8 * 8;
+  return 128 * 2 * ldbt + 4 * ldbt < (1LL << 31);
+}
 int proj_variant(const dcmesh_domain& d, int prec) {
   const int base = proj_variant_base(d, prec);
-  if (base == 4) return direct_proj_ok(d, prec) ? kProjDirect : wide_proj(d, prec);
+  if (base == 4) {
+    if (is_split(prec)) return direct_split_proj_ok(d) ? 4 : 0;
+    return direct_proj_ok(d, prec) ? kProjDirect : wide_proj(d, prec);
+  }
   return base + wide_proj(d, prec);
 }
 // The direct-LDS correction (launch keys 8 and 12: 8-byte and 16-byte
@@ -132,16 +141,20 @@ bool direct_corr_ok(const dcmesh_domain& d, int prec) {
 }
 int corr_variant(const dcmesh_domain& d, int prec) {
   const int base = corr_variant_base(d, prec);
-  if (base == 4) return direct_corr_ok(d, prec) ? (wide_corr(d, prec) ? 12 : 8) : wide_corr(d, prec);
+  if (base == 4) {
+    if (is_split(prec)) return 4;   // the split kernel with both tiles loaded into LDS directly
+    return direct_corr_ok(d, prec) ? (wide_corr(d, prec) ? 12 : 8) : wide_corr(d, prec);
+  }
   return base + wide_corr(d, prec);
 }
 int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
-  // FP16: the 32-deep LDS stage (variant 2) fits two waves per SIMD; the BF16
-  // build of it needs more registers and runs at one
-  if (is_split(prec)) return d.n_proj >= 96 ? (prec == DCMESH_SPLIT_FP16 ? 2 : 0) : 1;
+  // large tiles, BF16: the kernel with the projector planes loaded into LDS
+  // directly (proj_variant falls back to variant 0 where it cannot run); FP16:
+  // the 32-deep register-staged stage, which fits two waves per SIMD there
+  if (is_split(prec)) return d.n_proj >= 96 ? (prec == DCMESH_SPLIT_FP16 ? 2 : 4) : 1;
   const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
   // large tiles: the three-product kernel with direct LDS loads where the rows
   // allow it (proj_variant falls back to variant 0 otherwise)
@@ -151,7 +164,7 @@ int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
-  if (is_split(prec)) return 2 * d.n_orb > 128 ? 0 : 1;
+  if (is_split(prec)) return 2 * d.n_orb > 128 ? 4 : 1;   // 4: both tiles loaded into LDS directly
   const int n2 = 2 * d.n_orb;
   // large tiles: the three-product kernel with the Q tile loaded into LDS
   // directly (corr_variant falls back to variant 0 where it cannot run)
@@ -303,7 +316,8 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.a_stride = 3;
     D.ldq = (2 * D.n_orb + 3) / 4 * 4;
     D.ldq3 = (D.n_orb + 3) / 4 * 4;
-    D.ldbs = D.ldqt = (2 * (long long)D.n_proj + 7) / 8 * 8;
+    // whole 32-half stages of the split correction (zero padded)
+    D.ldbs = D.ldqt = (2 * (long long)D.n_proj + 31) / 32 * 32;
     D.ldbt = (2 * D.n_grid + 7) / 8 * 8;
   }
   P.any_proj = false;
@@ -795,7 +809,8 @@ void launch_project_split(const Ctx& c, int u_slot) {
       case 0: k_project_split<MODE, 128, 128, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 1: k_project_split<MODE, 64, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 2: k_project_split<MODE, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
-      default: k_project_split<MODE, 128, 256, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      case 3: k_project_split<MODE, 128, 256, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      default: k_project_split_dl<MODE, 128, 128><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
     }
   }
 }
@@ -814,7 +829,8 @@ void launch_correct_split(const Ctx& c, int out_slot) {
       case 0: k_correct_split<MODE, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       case 1: k_correct_split<MODE, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       case 2: k_correct_split<MODE, 64, 256, 64><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      default: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      case 3: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      default: k_correct_split_dl<MODE, 64, 256><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
     }
   }
 }

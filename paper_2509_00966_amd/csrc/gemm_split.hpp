@@ -448,4 +448,290 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
       }
 }
 
+// The split correction with both pre-split operands moved from memory
+// straight into LDS (buffer loads with an LDS destination), double-buffered
+// (one barrier per stage).  A stage covers 32 reduction indices: every row of
+// Bs and Qt contributes 64 B per plane, four 16-byte chunks.  One wave
+// instruction moves 16 rows; within a row, chunk c sits in slot c ^ ((r / 2) % 4)
+// so that the 16-byte fragment reads of eight consecutive rows fall on
+// distinct LDS banks.  The row length ldbs is a multiple of 32 halves (zero
+// padded), so no stage runs past it; rows past the grid or past 2 n_orb read
+// as zero and reach only outputs that are not stored.
+template <int MODE, int BMG, int BN>
+__global__ __launch_bounds__(kBlock) void k_correct_split_dl(const DomDesc* __restrict__ doms,
+                                                             const Item* __restrict__ items, int out_slot) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int KC = 32;
+  constexpr int TM = BMG / 32, TN = BN / 32;
+  constexpr int SA = BMG * KC, SB = BN * KC;
+  static_assert(BMG % 64 == 0 && BN % 64 == 0, "whole instructions per wave");
+  __shared__ __align__(16) T sA0h[SA], sA0l[SA], sA1h[SA], sA1l[SA];
+  __shared__ __align__(16) T sB0h[SB], sB0l[SB], sB1h[SB], sB1l[SB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const long long ldbs = D.ldbs, ldqt = D.ldqt;
+  const int no2 = 2 * D.n_orb;
+  const long long g0 = (long long)it.a * BMG;
+  const int j0 = it.b * BN;
+  const unsigned rowA = 2u * (unsigned)ldbs, rowB = 2u * (unsigned)ldqt;     // bytes per row
+  const unsigned nA = (unsigned)min((long long)BMG, D.n_grid - g0), nB = (unsigned)min(BN, no2 - j0);
+  const __amdgpu_buffer_rsrc_t rah = buffer_over((const DCM_GLOBAL char*)D.bs_hi + g0 * rowA, nA * rowA);
+  const __amdgpu_buffer_rsrc_t ral = buffer_over((const DCM_GLOBAL char*)D.bs_lo + g0 * rowA, nA * rowA);
+  const __amdgpu_buffer_rsrc_t rbh = buffer_over((const DCM_GLOBAL char*)D.qt_hi + (long long)j0 * rowB, nB * rowB);
+  const __amdgpu_buffer_rsrc_t rbl = buffer_over((const DCM_GLOBAL char*)D.qt_lo + (long long)j0 * rowB, nB * rowB);
+  float* __restrict__ out = (float*)D.slot[out_slot];
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = (wv / 2) * (BMG / 2), wn0 = (wv % 2) * (BN / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  // this lane's row within an instruction's 16 rows and the chunk it moves
+  const int lr = lane / 4;
+  const unsigned lchunk = (unsigned)((lane % 4) ^ ((lr >> 1) & 3));
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  auto issue = [&](int st, T* ah, T* al, T* bh, T* bl) {
+    const unsigned kb = (unsigned)st * (2u * KC) + 16u * lchunk;            // byte offset in the row
+#pragma unroll
+    for (int r0 = wv * 16; r0 < BMG; r0 += 64) {
+      const unsigned off = (unsigned)(r0 + lr) * rowA + kb;
+      load_lds16(rah, (float*)(ah + r0 * KC), off);
+      load_lds16(ral, (float*)(al + r0 * KC), off);
+    }
+#pragma unroll
+    for (int r0 = wv * 16; r0 < BN; r0 += 64) {
+      const unsigned off = (unsigned)(r0 + lr) * rowB + kb;
+      load_lds16(rbh, (float*)(bh + r0 * KC), off);
+      load_lds16(rbl, (float*)(bl + r0 * KC), off);
+    }
+  };
+  auto frag = [&](const T* s, int r) -> V8 {
+    return *(const V8*)&s[r * KC + 8 * (lk ^ ((r >> 1) & 3))];
+  };
+  auto compute = [&](const T* ah_s, const T* al_s, const T* bh_s, const T* bl_s) {
+    V8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      ah[i] = frag(ah_s, wm0 + i * 16 + ll);
+      al[i] = frag(al_s, wm0 + i * 16 + ll);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      bh[j] = frag(bh_s, wn0 + j * 16 + ll);
+      bl[j] = frag(bl_s, wn0 + j * 16 + ll);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = Half<MODE>::mma(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(al[i], bh[j], acc[i][j]);
+      }
+  };
+  const int n_st = (int)(ldbs / KC);
+  if (n_st > 0) issue(0, sA0h, sA0l, sB0h, sB0l);
+  int st = 0;
+  for (; st + 1 < n_st; st += 2) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+    issue(st + 1, sA1h, sA1l, sB1h, sB1l);
+    compute(sA0h, sA0l, sB0h, sB0l);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (st + 2 < n_st) issue(st + 2, sA0h, sA0l, sB0h, sB0l);
+    compute(sA1h, sA1l, sB1h, sB1l);
+  }
+  if (st < n_st) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    compute(sA0h, sA0l, sB0h, sB0l);
+  }
+  const float unscale = MODE == 1 ? 1.0f / (fp16_scale_from_bits(D.maxbits[0]) * fp16_scale_from_bits(D.maxbits[2]))
+                                  : 1.0f;
+  // out += acc, one 16-row tile at a time (reads before writes)
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    float prev[TN][4];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        prev[j][r] = (g < D.n_grid && jj < no2) ? out[g * no2 + jj] : 0.f;
+      }
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && jj < no2) out[g * no2 + jj] = prev[j][r] + acc[i][j][r] * unscale;
+      }
+  }
+}
+
+// The split projection with the pre-split projector planes Bt moved from
+// memory straight into LDS (buffer loads with an LDS destination, rows of 64 B
+// per stage, chunks swizzled as in k_correct_split_dl) and u split on the way
+// into LDS as in k_project_split; both tiles double-buffered (one barrier per
+// stage).  Reduction indices past the split's last grid point meet a zero u
+// tile; rows past n_proj read as zero.  Items as k_project_split.
+template <int MODE, int BM, int BN>
+__global__ __launch_bounds__(kBlock) void k_project_split_dl(const DomDesc* __restrict__ doms,
+                                                             const Item* __restrict__ items, int u_slot) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int KG = 16, KK = 2 * KG;        // grid points and reduction indices per stage
+  constexpr int LK = KK + 8;                 // padded u rows (halves)
+  constexpr int TM = BM / 32, TN = BN / 32;
+  constexpr int VB = KG * BN / 2;
+  constexpr int RB = (VB + kBlock - 1) / kBlock;
+  constexpr int SA = BM * KK, SB = BN * LK;
+  static_assert(BM % 64 == 0, "whole instructions per wave");
+  __shared__ __align__(16) T sA0h[SA], sA0l[SA], sA1h[SA], sA1l[SA];
+  __shared__ __align__(16) T sB0h[SB], sB0l[SB], sB1h[SB], sB1l[SB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no2 = 2 * D.n_orb;
+  const int p0 = it.a * BM, j0 = it.b * BN;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+  const int n_st = (int)((g_end - g_begin + KG - 1) / KG);
+  const unsigned rowA = 2u * (unsigned)D.ldbt;                           // bytes per Bt row
+  const unsigned nA = (unsigned)min(BM, np - p0);
+  const long long kb0 = 2 * (2 * g_begin);                                // byte offset of the split in a row
+  const __amdgpu_buffer_rsrc_t rah = buffer_over((const DCM_GLOBAL char*)D.bt_hi + (long long)p0 * rowA, nA * rowA);
+  const __amdgpu_buffer_rsrc_t ral = buffer_over((const DCM_GLOBAL char*)D.bt_lo + (long long)p0 * rowA, nA * rowA);
+  const float2* __restrict__ U = (const float2*)D.slot[u_slot];
+  const float su = MODE == 1 ? fp16_scale_from_bits(D.maxbits[1]) : 1.0f;
+  const float sbs = MODE == 1 ? fp16_scale_from_bits(D.maxbits[0]) : 1.0f;
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BN / 2);
+  const int ll = lane % 16, lk = lane / 16;
+  const int lr = lane / 4;
+  const unsigned lchunk = (unsigned)((lane % 4) ^ ((lr >> 1) & 3));
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  float2 rb[RB];
+  auto issue_a = [&](int st, T* ah, T* al) {
+    const unsigned kb = (unsigned)(kb0 + (long long)st * (2 * KK)) + 16u * lchunk;
+#pragma unroll
+    for (int r0 = wv * 16; r0 < BM; r0 += 64) {
+      const unsigned off = (unsigned)(r0 + lr) * rowA + kb;
+      load_lds16(rah, (float*)(ah + r0 * KK), off);
+      load_lds16(ral, (float*)(al + r0 * KK), off);
+    }
+  };
+  auto load_b = [&](int st) {
+    const long long gc = g_begin + (long long)st * KG;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+      const long long g = gc + gl;
+      const int j = j0 + 2 * nn;
+      rb[q] = (idx < VB && g < g_end && j < no2) ? U[g * (no2 / 2) + j / 2] : make_float2(0.f, 0.f);
+    }
+  };
+  auto store_b = [&](T* bh, T* bl) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+        T rh, rl, ih, il;
+        split2<MODE>(rb[q].x, su, rh, rl);
+        split2<MODE>(rb[q].y, su, ih, il);
+        const T nrh = (T)(-(float)rh), nrl = (T)(-(float)rl);
+        const int c0 = (2 * nn) * LK + 2 * gl, c1 = (2 * nn + 1) * LK + 2 * gl;
+        *(Pair<T>*)&bh[c0] = Pair<T>{rh, ih};
+        *(Pair<T>*)&bh[c1] = Pair<T>{ih, nrh};
+        *(Pair<T>*)&bl[c0] = Pair<T>{rl, il};
+        *(Pair<T>*)&bl[c1] = Pair<T>{il, nrl};
+      }
+    }
+  };
+  auto compute = [&](const T* ah_s, const T* al_s, const T* bh_s, const T* bl_s) {
+    V8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm0 + i * 16 + ll;
+      const int o = r * KK + 8 * (lk ^ ((r >> 1) & 3));
+      ah[i] = *(const V8*)&ah_s[o];
+      al[i] = *(const V8*)&al_s[o];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int o = (wn0 + j * 16 + ll) * LK + 8 * lk;
+      bh[j] = *(const V8*)&bh_s[o];
+      bl[j] = *(const V8*)&bl_s[o];
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = Half<MODE>::mma(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(al[i], bh[j], acc[i][j]);
+      }
+  };
+  if (n_st > 0) {
+    issue_a(0, sA0h, sA0l);
+    load_b(0);
+  }
+  // the scheduling barriers keep the split of the next u tile (which waits
+  // for its loads) behind the products of the current one
+  int st = 0;
+  for (; st + 1 < n_st; st += 2) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    store_b(sB0h, sB0l);
+    __syncthreads();
+    issue_a(st + 1, sA1h, sA1l);
+    load_b(st + 1);
+    compute(sA0h, sA0l, sB0h, sB0l);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store_b(sB1h, sB1l);
+    __syncthreads();
+    if (st + 2 < n_st) {
+      issue_a(st + 2, sA0h, sA0l);
+      load_b(st + 2);
+    }
+    compute(sA1h, sA1l, sB1h, sB1l);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (st < n_st) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    store_b(sB0h, sB0l);
+    __syncthreads();
+    compute(sA0h, sA0l, sB0h, sB0l);
+  }
+  const float unscale = 1.0f / (su * sbs);
+  float* __restrict__ part = (float*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (p < np && jj < no2) part[(long long)p * no2 + jj] = acc[i][j][r] * unscale;
+      }
+}
+
 }  // namespace dcm
+

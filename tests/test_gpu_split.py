@@ -32,16 +32,23 @@ def _dom(seed=51):
     return make_domain(seed, (19, 13, 21), 21, 3, proj_per_atom=8, h=0.4, fd_order=6)
 
 
+@pytest.mark.parametrize("corr_variant", [-1, 0, 1, 2, 3, 4])
 @pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
-def test_split_hpsi_matches_split_reference(api, precision, mode):
+def test_split_hpsi_matches_split_reference(api, precision, mode, corr_variant):
+    """Every correction tile variant (4: both tiles loaded into LDS directly);
+    21 orbitals and 24 projectors leave partial tiles in both dimensions."""
     import torch
     dom = _dom()
     A = np.array([0.05, -0.11, 0.23])
     g = to_device(dom, precision)
     ws = api.Workspace.for_domains([g], precision)
     hp = torch.empty_like(g.psi)
-    api.density([g], a_tensor(A[None]), precision, ws, [dict(hpsi_occ=hp)])
-    torch.cuda.synchronize()
+    try:
+        api.set_tuning("correct", corr_variant)
+        api.density([g], a_tensor(A[None]), precision, ws, [dict(hpsi_occ=hp)])
+        torch.cuda.synchronize()
+    finally:
+        api.set_tuning("correct", -1)
     od = dom.rounded(np.float32)
     ref = (H.apply_hloc(od, A, od.psi) * od.occ[None, :]
            + S.apply_vnl_split(od, od.psi, mode, occ_scale=True))
@@ -51,6 +58,34 @@ def test_split_hpsi_matches_split_reference(api, precision, mode):
     nl = np.linalg.norm(S.apply_vnl_split(od, od.psi, mode, occ_scale=True) - H.apply_vnl(od, od.psi) * od.occ)
     assert nl > 0
     assert rel_fro(_np(hp), exact) < (2e-4 if mode == "bf16" else 2e-5)
+
+
+@pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
+def test_split_projection_variants_match_split_reference(api, precision, mode, proj_variant):
+    """Every projection tile variant (4: the projector planes loaded into LDS
+    directly) on two domains: 24 projectors / 21 orbitals (one partial tile)
+    and 136 projectors / 70 orbitals (a second tile in both dimensions with a
+    ragged edge); both grids end in a partial stage."""
+    import torch
+    doms = [_dom(), make_domain(52, (18, 17, 16), 70, 17, proj_per_atom=8, h=0.4, fd_order=4)]
+    A = np.array([0.05, -0.11, 0.23])
+    g = [to_device(d, precision) for d in doms]
+    ws = api.Workspace.for_domains(g, precision)
+    hp = [torch.empty_like(x.psi) for x in g]
+    try:
+        api.set_tuning("project", proj_variant)
+        api.density(g, a_tensor(np.stack([A, -A])), precision, ws, [dict(hpsi_occ=h) for h in hp],
+                    a_per_domain=True)
+        torch.cuda.synchronize()
+    finally:
+        api.set_tuning("project", -1)
+    for i, dom in enumerate(doms):
+        od = dom.rounded(np.float32)
+        a = A if i == 0 else -A
+        ref = (H.apply_hloc(od, a, od.psi) * od.occ[None, :]
+               + S.apply_vnl_split(od, od.psi, mode, occ_scale=True))
+        assert rel_fro(_np(hp[i]), ref) < 2e-6, i
 
 
 @pytest.mark.parametrize("precision,tol", [("split_bf16", 1e-4), ("split_fp16", 1e-5)])
