@@ -422,11 +422,11 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     });
     group_launch(P.absmax_b, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
       const DomDesc& D = P.desc[i];
-      for (long long b = 0; b < cdiv(D.n_grid * 2 * D.n_proj, (long long)kBlock * 16); ++b) it.push_back({i, (int)b, 0, 0});
+      for (long long b = 0; b < cdiv(D.n_grid * 2 * D.n_proj, (long long)kBlock * kAbsPer); ++b) it.push_back({i, (int)b, 0, 0});
     });
     group_launch(P.absmax_u, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
       const DomDesc& D = P.desc[i];
-      for (long long b = 0; b < cdiv(D.n_grid * 2 * D.n_orb, (long long)kBlock * 16); ++b) it.push_back({i, (int)b, 0, 0});
+      for (long long b = 0; b < cdiv(D.n_grid * 2 * D.n_orb, (long long)kBlock * kAbsPer); ++b) it.push_back({i, (int)b, 0, 0});
     });
     group_launch(P.splitq, P.items, n_dom, has_p, [&](int i, std::vector<Item>& it) {
       const DomDesc& D = P.desc[i];

@@ -65,27 +65,43 @@ __device__ __forceinline__ float fp16_scale_from_bits(unsigned bits) {
 }
 
 // max |x| over a real array of n values into *bits (atomic max on the float
-// bits, exact and order independent).  Items: (dom, block); which: 0 = B, 1 = slot u.
+// bits, exact and order independent).  Items: (dom, block of kBlock kAbsPer
+// values); which: 0 = B, 1 = slot u.  A block whose max does not exceed the
+// value already stored skips its atomic, so the thousands of blocks of a
+// large array do not queue on one address.
+constexpr int kAbsPer = 64;
 __global__ __launch_bounds__(kBlock) void k_absmax(const DomDesc* __restrict__ doms, const Item* __restrict__ items,
                                                    int which, int u_slot) {
-  __shared__ float red[4];
+  __shared__ float red[kBlock / kWave];
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
-  const float* x = which == 0 ? (const float*)D.proj : (const float*)D.slot[u_slot];
+  const DCM_GLOBAL float* x = which == 0 ? (const DCM_GLOBAL float*)D.proj : (const DCM_GLOBAL float*)D.slot[u_slot];
   const long long n = which == 0 ? D.n_grid * 2 * D.n_proj : D.n_grid * 2 * D.n_orb;
+  const long long base = (long long)it.a * kBlock * kAbsPer;
   float m = 0.f;
-  const long long base = (long long)it.a * kBlock * 16;
-  for (int i = 0; i < 16; ++i) {
-    const long long e = base + (long long)i * kBlock + threadIdx.x;
-    if (e < n) m = fmaxf(m, fabsf(x[e]));
+  if ((reinterpret_cast<uintptr_t>(x) & 15) == 0 && base + kBlock * kAbsPer <= n) {
+    const DCM_GLOBAL float4* x4 = (const DCM_GLOBAL float4*)(x + base);
+#pragma unroll
+    for (int i = 0; i < kAbsPer / 4; ++i) {
+      const float4 v = x4[i * kBlock + threadIdx.x];
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+  } else {
+    for (int i = 0; i < kAbsPer; ++i) {
+      const long long e = base + (long long)i * kBlock + threadIdx.x;
+      if (e < n) m = fmaxf(m, fabsf(x[e]));
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const float b = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    atomicMax(&D.maxbits[which == 0 ? 0 : 1], __float_as_uint(b));
+    float b = red[0];
+    for (int w = 1; w < kBlock / kWave; ++w) b = fmaxf(b, red[w]);
+    unsigned* dst = &D.maxbits[which == 0 ? 0 : 1];
+    const unsigned bits = __float_as_uint(b);
+    if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, bits);
   }
 }
 
