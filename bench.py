@@ -229,11 +229,14 @@ def measured_traffic(family, prec):
     m = re.search(r"kernel source hash: `([0-9a-f]+)`", text)
     if not m or m.group(1) != kernel_source_hash():
         return None
+    col = None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 6 and cells[0] == family and cells[1] == prec:
+        if "HBM bytes per launch" in cells:
+            col = cells.index("HBM bytes per launch")
+        elif col is not None and len(cells) > col and cells[0] == family and cells[1] == prec:
             try:
-                return float(cells[5])
+                return float(cells[col])
             except ValueError:
                 return None
     return None
