@@ -86,9 +86,13 @@ constexpr int kProjDirect = 8; // its launch key
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 // split-precision kernels (variant 2 of each stages twice as much per LDS pass)
 const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}};
-const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}};
+const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}, {64, 256}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
-constexpr int kNCorr = 5;      // FP32 variant 4: the three-product kernel with the Q tile loaded into LDS directly
+// FP32 variant 4: the three-product kernel with the Q tile loaded into LDS
+// directly.  Split variants 4 and 5: both tiles loaded into LDS directly, on
+// four waves with two stages and on eight waves with three (other modes run
+// variant 5 as 4).
+constexpr int kNCorr = 6;
 constexpr int kProjKG = 16;
 
 std::atomic<int> g_tune[4] = {{-1}, {-1}, {-1}, {-1}};
@@ -140,7 +144,11 @@ bool direct_corr_ok(const dcmesh_domain& d, int prec) {
   return prec == DCMESH_FP32 && (long long)d.n_proj * ldq3 * 4 < (1LL << 31);
 }
 int corr_variant(const dcmesh_domain& d, int prec) {
-  const int base = corr_variant_base(d, prec);
+  int base = corr_variant_base(d, prec);
+  if (base == 5) {
+    if (is_split(prec)) return 5;
+    base = 4;
+  }
   if (base == 4) {
     if (is_split(prec)) return 4;   // the split kernel with both tiles loaded into LDS directly
     return direct_corr_ok(d, prec) ? (wide_corr(d, prec) ? 12 : 8) : wide_corr(d, prec);
@@ -164,7 +172,8 @@ int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
-  if (is_split(prec)) return 2 * d.n_orb > 128 ? 4 : 1;   // 4: both tiles loaded into LDS directly
+  // large tiles: both tiles loaded into LDS directly, three stages on eight waves
+  if (is_split(prec)) return 2 * d.n_orb > 128 ? 5 : 1;
   const int n2 = 2 * d.n_orb;
   // large tiles: the three-product kernel with the Q tile loaded into LDS
   // directly (corr_variant falls back to variant 0 where it cannot run)
@@ -362,7 +371,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_e_nl++;
   auto cv = [&](int i) { return doms[i].n_proj > 0 ? corr_variant(doms[i], prec) : -1; };
   group_launch(P.corr, P.items, n_dom, cv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i) % 4] : is_split(prec) ? kCorrSplit[cv(i) % 4] : kCorrF32[cv(i) % 4];
+    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i) % 4] : is_split(prec) ? kCorrSplit[cv(i)] : kCorrF32[cv(i) % 4];
     const DomDesc& D = P.desc[i];
     for (long long gt = 0; gt < cdiv(D.n_grid, t.bm); ++gt)
       for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, (int)gt, nt, 0});
@@ -830,7 +839,8 @@ void launch_correct_split(const Ctx& c, int out_slot) {
       case 1: k_correct_split<MODE, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       case 2: k_correct_split<MODE, 64, 256, 64><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       case 3: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      default: k_correct_split_dl<MODE, 64, 256><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      case 4: k_correct_split_dl<MODE, 64, 256><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+      default: k_correct_split_dl3<MODE><<<g, dim3(kBlockCorr3), 0, c.s>>>(c.d_desc, it, out_slot); break;
     }
   }
 }

@@ -593,6 +593,184 @@ __global__ __launch_bounds__(kBlock) void k_correct_split_dl(const DomDesc* __re
   }
 }
 
+// The split correction on eight waves with a three-deep ring of LDS stages:
+// the Bs rows of a stage are requested two stages ahead (straight into LDS),
+// which hides the memory latency that one stage of compute cannot; the small
+// Qt tile comes from L2 one stage ahead through registers.  A 128 x 256 tile
+// (waves 2 x 4, each 64 x 64); per stage every wave moves one 16-row group of
+// each Bs plane.  Layout, swizzle and zero fill as k_correct_split_dl.  512
+// threads.
+constexpr int kBlockCorr3 = 512;
+template <int MODE>
+__global__ __launch_bounds__(kBlockCorr3) void k_correct_split_dl3(const DomDesc* __restrict__ doms,
+                                                                   const Item* __restrict__ items, int out_slot) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int BMG = 128, BN = 256, KC = 32, NW = kBlockCorr3 / kWave;
+  constexpr int TM = 4, TN = 4;
+  constexpr int SA = BMG * KC, SB = BN * KC;
+  __shared__ __align__(16) T sA0h[SA], sA0l[SA], sA1h[SA], sA1l[SA], sA2h[SA], sA2l[SA];
+  __shared__ __align__(16) T sB0h[SB], sB0l[SB], sB1h[SB], sB1l[SB], sB2h[SB], sB2l[SB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const long long ldbs = D.ldbs, ldqt = D.ldqt;
+  const int no2 = 2 * D.n_orb;
+  const long long g0 = (long long)it.a * BMG;
+  const int j0 = it.b * BN;
+  const unsigned rowA = 2u * (unsigned)ldbs, rowB = 2u * (unsigned)ldqt;     // bytes per row
+  const unsigned nA = (unsigned)min((long long)BMG, D.n_grid - g0), nB = (unsigned)min(BN, no2 - j0);
+  const __amdgpu_buffer_rsrc_t rah = buffer_over((const DCM_GLOBAL char*)D.bs_hi + g0 * rowA, nA * rowA);
+  const __amdgpu_buffer_rsrc_t ral = buffer_over((const DCM_GLOBAL char*)D.bs_lo + g0 * rowA, nA * rowA);
+  const __amdgpu_buffer_rsrc_t rbh = buffer_over((const DCM_GLOBAL char*)D.qt_hi + (long long)j0 * rowB, nB * rowB);
+  const __amdgpu_buffer_rsrc_t rbl = buffer_over((const DCM_GLOBAL char*)D.qt_lo + (long long)j0 * rowB, nB * rowB);
+  float* __restrict__ out = (float*)D.slot[out_slot];
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = (wv / 4) * 64, wn0 = (wv % 4) * 64;
+  const int ll = lane % 16, lk = lane / 16;
+  const int lr = lane / 4;
+  const unsigned lchunk = (unsigned)((lane % 4) ^ ((lr >> 1) & 3));
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  // Qt tile rows through registers (it sits in L2): 4 x 16 bytes per thread
+  // per stage, stored into LDS swizzled like the Bs rows
+  const DCM_GLOBAL T* qh = (const DCM_GLOBAL T*)D.qt_hi + (long long)j0 * ldqt;
+  const DCM_GLOBAL T* ql = (const DCM_GLOBAL T*)D.qt_lo + (long long)j0 * ldqt;
+  V8 rq[4];
+  const V8 z8 = {};
+  auto load_b = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = (q % 2) * kBlockCorr3 + threadIdx.x;
+      const int row = idx / 4, ch = idx % 4;
+      // rows past the tile read the last valid row; store_b zeroes them
+      const int rr = min(row, (int)nB - 1);
+      rq[q] = *(const DCM_GLOBAL V8*)((q < 2 ? qh : ql) + (long long)rr * ldqt + st * KC + 8 * ch);
+    }
+  };
+  auto store_b = [&](T* bh, T* bl) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = (q % 2) * kBlockCorr3 + threadIdx.x;
+      const int row = idx / 4, ch = idx % 4;
+      *(V8*)&(q < 2 ? bh : bl)[row * KC + 8 * (ch ^ ((row >> 1) & 3))] = row < (int)nB ? rq[q] : z8;
+    }
+  };
+  auto issue_a = [&](int st, T* ah, T* al) {
+    const unsigned kb = (unsigned)st * (2u * KC) + 16u * lchunk;
+    const int ra = wv * 16;
+    const unsigned oa = (unsigned)(ra + lr) * rowA + kb;
+    load_lds16(rah, (float*)(ah + ra * KC), oa);
+    load_lds16(ral, (float*)(al + ra * KC), oa);
+  };
+  auto frag = [&](const T* s, int r) -> V8 {
+    return *(const V8*)&s[r * KC + 8 * (lk ^ ((r >> 1) & 3))];
+  };
+  auto compute = [&](const T* ah_s, const T* al_s, const T* bh_s, const T* bl_s) {
+    V8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      ah[i] = frag(ah_s, wm0 + i * 16 + ll);
+      al[i] = frag(al_s, wm0 + i * 16 + ll);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      bh[j] = frag(bh_s, wn0 + j * 16 + ll);
+      bl[j] = frag(bl_s, wn0 + j * 16 + ll);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = Half<MODE>::mma(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(al[i], bh[j], acc[i][j]);
+      }
+  };
+  // Stage st: its Bs part was requested two stages earlier (the only load
+  // that may still be in flight is the one of stage st + 1: two per wave) and
+  // its Qt part was stored by this wave at the end of stage st - 1.  After
+  // the barrier: request Qt of st + 1 and Bs of st + 2 (into the buffer that
+  // stage st - 1 read), multiply, store Qt of st + 1.  The barrier is the
+  // bare instruction between two compiler memory clobbers: a workgroup fence
+  // would wait for every load in flight.
+  const int n_st = (int)(ldbs / KC);    // >= 1: the kernel runs only where n_proj > 0
+  issue_a(0, sA0h, sA0l);
+  load_b(0);
+  if (n_st > 1) issue_a(1, sA1h, sA1l);
+  store_b(sB0h, sB0l);
+#define DCM_SYNC(MORE)                                                              \
+  do {                                                                              \
+    if (MORE)                                                                       \
+      __builtin_amdgcn_s_waitcnt(0x0072);   /* vmcnt(2) lgkmcnt(0) */               \
+    else                                                                            \
+      __builtin_amdgcn_s_waitcnt(0x0070);   /* vmcnt(0) lgkmcnt(0) */               \
+    asm volatile("" ::: "memory");                                                  \
+    __builtin_amdgcn_s_barrier();                                                   \
+    asm volatile("" ::: "memory");                                                  \
+  } while (0)
+#define DCM_STAGE_FULL(ST, C, N, NB)                                                \
+  do {                                                                              \
+    DCM_SYNC(true);                                                                 \
+    load_b((ST) + 1);                                                               \
+    __builtin_amdgcn_sched_barrier(0);   /* Qt loads retire before the Bs ones */   \
+    issue_a((ST) + 2, sA##N##h, sA##N##l);                                          \
+    compute(sA##C##h, sA##C##l, sB##C##h, sB##C##l);                                \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    store_b(sB##NB##h, sB##NB##l);                                                  \
+  } while (0)
+#define DCM_STAGE_TAIL(ST, C, N, NB)                                                \
+  do {                                                                              \
+    DCM_SYNC((ST) + 1 < n_st);                                                      \
+    if ((ST) + 1 < n_st) load_b((ST) + 1);                                          \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    if ((ST) + 2 < n_st) issue_a((ST) + 2, sA##N##h, sA##N##l);                     \
+    compute(sA##C##h, sA##C##l, sB##C##h, sB##C##l);                                \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    if ((ST) + 1 < n_st) store_b(sB##NB##h, sB##NB##l);                             \
+  } while (0)
+  int st = 0;
+  for (; st + 4 < n_st; st += 3) {
+    DCM_STAGE_FULL(st, 0, 2, 1);
+    DCM_STAGE_FULL(st + 1, 1, 0, 2);
+    DCM_STAGE_FULL(st + 2, 2, 1, 0);
+  }
+  if (st < n_st) DCM_STAGE_TAIL(st, 0, 2, 1);
+  if (st + 1 < n_st) DCM_STAGE_TAIL(st + 1, 1, 0, 2);
+  if (st + 2 < n_st) DCM_STAGE_TAIL(st + 2, 2, 1, 0);
+  if (st + 3 < n_st) DCM_STAGE_TAIL(st + 3, 0, 2, 1);
+#undef DCM_STAGE_FULL
+#undef DCM_STAGE_TAIL
+#undef DCM_SYNC
+  const float unscale = MODE == 1 ? 1.0f / (fp16_scale_from_bits(D.maxbits[0]) * fp16_scale_from_bits(D.maxbits[2]))
+                                  : 1.0f;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    float prev[TN][4];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        prev[j][r] = (g < D.n_grid && jj < no2) ? out[g * no2 + jj] : 0.f;
+      }
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (g < D.n_grid && jj < no2) out[g * no2 + jj] = prev[j][r] + acc[i][j][r] * unscale;
+      }
+  }
+}
+
 // The split projection with the pre-split projector planes Bt moved from
 // memory straight into LDS (buffer loads with an LDS destination, rows of 64 B
 // per stage, chunks swizzled as in k_correct_split_dl) and u split on the way

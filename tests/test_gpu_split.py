@@ -32,11 +32,12 @@ def _dom(seed=51):
     return make_domain(seed, (19, 13, 21), 21, 3, proj_per_atom=8, h=0.4, fd_order=6)
 
 
-@pytest.mark.parametrize("corr_variant", [-1, 0, 1, 2, 3, 4])
+@pytest.mark.parametrize("corr_variant", [-1, 0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
 def test_split_hpsi_matches_split_reference(api, precision, mode, corr_variant):
-    """Every correction tile variant (4: both tiles loaded into LDS directly);
-    21 orbitals and 24 projectors leave partial tiles in both dimensions."""
+    """Every correction tile variant (4 and 5: both tiles loaded into LDS
+    directly, two-stage on four waves and three-stage on eight); 21 orbitals
+    and 24 projectors leave partial tiles in both dimensions."""
     import torch
     dom = _dom()
     A = np.array([0.05, -0.11, 0.23])
@@ -58,6 +59,33 @@ def test_split_hpsi_matches_split_reference(api, precision, mode, corr_variant):
     nl = np.linalg.norm(S.apply_vnl_split(od, od.psi, mode, occ_scale=True) - H.apply_vnl(od, od.psi) * od.occ)
     assert nl > 0
     assert rel_fro(_np(hp), exact) < (2e-4 if mode == "bf16" else 2e-5)
+
+
+@pytest.mark.parametrize("corr_variant", [4, 5])
+@pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
+def test_split_correction_stage_counts(api, precision, mode, corr_variant):
+    """The correction kernels that load both tiles into LDS directly, over
+    reductions of 9, 10 and 11 stages of 32 (136, 160 and 168 projectors):
+    the three-stage ring ends on each of its three buffers; 70 orbitals give a
+    ragged second column tile for the four-wave kernel."""
+    import torch
+    doms = [make_domain(53 + k, (12, 11, 13), 70, na, proj_per_atom=8, h=0.4, fd_order=4)
+            for k, na in enumerate((17, 20, 21))]
+    A = np.array([0.05, -0.11, 0.23])
+    g = [to_device(d, precision) for d in doms]
+    ws = api.Workspace.for_domains(g, precision)
+    hp = [torch.empty_like(x.psi) for x in g]
+    try:
+        api.set_tuning("correct", corr_variant)
+        api.density(g, a_tensor(A[None]), precision, ws, [dict(hpsi_occ=h) for h in hp])
+        torch.cuda.synchronize()
+    finally:
+        api.set_tuning("correct", -1)
+    for i, dom in enumerate(doms):
+        od = dom.rounded(np.float32)
+        ref = (H.apply_hloc(od, A, od.psi) * od.occ[None, :]
+               + S.apply_vnl_split(od, od.psi, mode, occ_scale=True))
+        assert rel_fro(_np(hp[i]), ref) < 2e-6, i
 
 
 @pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4])
