@@ -81,11 +81,15 @@ struct GemmVariant { int bm, bn; };
 // in complex orbitals is half the real-column tile listed here.
 const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
-constexpr int kNProj = 5;      // FP32 variant 4: the three-product kernel with direct LDS loads
+// FP32 variant 4: the three-product kernel with direct LDS loads.  Split
+// variants 4 and 5: the projector planes loaded into LDS directly, on four
+// waves with two stages and on eight waves with three (other modes run
+// variant 5 as 4).
+constexpr int kNProj = 6;
 constexpr int kProjDirect = 8; // its launch key
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 // split-precision kernels (variant 2 of each stages twice as much per LDS pass)
-const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}};
+const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}, {128, 128}, {128, 256}};
 const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}, {64, 256}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
 // FP32 variant 4: the three-product kernel with the Q tile loaded into LDS
@@ -130,7 +134,11 @@ bool direct_split_proj_ok(const dcmesh_domain& d) {
   return 128 * 2 * ldbt + 4 * ldbt < (1LL << 31);
 }
 int proj_variant(const dcmesh_domain& d, int prec) {
-  const int base = proj_variant_base(d, prec);
+  int base = proj_variant_base(d, prec);
+  if (base == 5) {
+    if (is_split(prec)) return direct_split_proj_ok(d) ? 5 : 0;
+    base = 4;
+  }
   if (base == 4) {
     if (is_split(prec)) return direct_split_proj_ok(d) ? 4 : 0;
     return direct_proj_ok(d, prec) ? kProjDirect : wide_proj(d, prec);
@@ -159,10 +167,9 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
-  // large tiles, BF16: the kernel with the projector planes loaded into LDS
-  // directly (proj_variant falls back to variant 0 where it cannot run); FP16:
-  // the 32-deep register-staged stage, which fits two waves per SIMD there
-  if (is_split(prec)) return d.n_proj >= 96 ? (prec == DCMESH_SPLIT_FP16 ? 2 : 4) : 1;
+  // large tiles: the projector planes loaded into LDS directly, three stages
+  // on eight waves (proj_variant falls back to variant 0 where it cannot run)
+  if (is_split(prec)) return d.n_proj >= 96 ? 5 : 1;
   const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
   // large tiles: the three-product kernel with direct LDS loads where the rows
   // allow it (proj_variant falls back to variant 0 otherwise)
@@ -352,7 +359,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
 
   auto pv = [&](int i) { return doms[i].n_proj > 0 ? proj_variant(doms[i], prec) : -1; };
   group_launch(P.proj, P.items, n_dom, pv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i) % 4] : is_split(prec) ? kProjSplit[pv(i) % 4] : kProjF32[pv(i) % 4];
+    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i) % 4] : is_split(prec) ? kProjSplit[pv(i)] : kProjF32[pv(i) % 4];
     const DomDesc& D = P.desc[i];
     const size_t b0 = it.size();
     const int nmt = (int)cdiv(D.n_proj, t.bm), nnt = (int)cdiv(2 * D.n_orb, t.bn);
@@ -819,7 +826,8 @@ void launch_project_split(const Ctx& c, int u_slot) {
       case 1: k_project_split<MODE, 64, 64, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 2: k_project_split<MODE, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 3: k_project_split<MODE, 128, 256, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
-      default: k_project_split_dl<MODE, 128, 128><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      case 4: k_project_split_dl<MODE, 128, 128><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      default: k_project_split_dl3<MODE><<<g, dim3(kBlockProj3), 0, c.s>>>(c.d_desc, it, u_slot); break;
     }
   }
 }

@@ -927,5 +927,185 @@ __global__ __launch_bounds__(kBlock) void k_project_split_dl(const DomDesc* __re
       }
 }
 
+// The split projection on eight waves with the ring of k_correct_split_dl3:
+// the Bt rows of a stage (the large operand) are requested two stages ahead
+// straight into a three-deep LDS ring; u comes one stage ahead through
+// registers and is split into hi/lo on its way into a two-deep ring (a
+// buffer is free once the barrier after its last reader has passed), so the
+// loop is unrolled by six.  A 128 x 256 tile (waves 2 x 4, each 64 x 64); a
+// stage covers 16 grid points.  Reduction indices past the split meet a zero
+// u tile; rows past n_proj read as zero.  Items as k_project_split; 512
+// threads.
+constexpr int kBlockProj3 = 512;
+template <int MODE>
+__global__ __launch_bounds__(kBlockProj3) void k_project_split_dl3(const DomDesc* __restrict__ doms,
+                                                                   const Item* __restrict__ items, int u_slot) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int BM = 128, BN = 256, KG = 16, KK = 2 * KG, LK = KK + 8;
+  constexpr int TM = 4, TN = 4;
+  constexpr int SA = BM * KK, SB = BN * LK;
+  constexpr int RB = KG * (BN / 2) / kBlockProj3;      // complex values of u per thread and stage
+  __shared__ __align__(16) T sA0h[SA], sA0l[SA], sA1h[SA], sA1l[SA], sA2h[SA], sA2l[SA];
+  __shared__ __align__(16) T sB0h[SB], sB0l[SB], sB1h[SB], sB1l[SB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no2 = 2 * D.n_orb, no = D.n_orb;
+  const int p0 = it.a * BM, j0 = it.b * BN;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+  const int n_st = (int)((g_end - g_begin + KG - 1) / KG);              // >= 1
+  const unsigned rowA = 2u * (unsigned)D.ldbt;
+  const unsigned nA = (unsigned)min(BM, np - p0);
+  const long long kb0 = 2 * (2 * g_begin);
+  const __amdgpu_buffer_rsrc_t rah = buffer_over((const DCM_GLOBAL char*)D.bt_hi + (long long)p0 * rowA, nA * rowA);
+  const __amdgpu_buffer_rsrc_t ral = buffer_over((const DCM_GLOBAL char*)D.bt_lo + (long long)p0 * rowA, nA * rowA);
+  const DCM_GLOBAL float2* U = (const DCM_GLOBAL float2*)D.slot[u_slot];
+  const float su = MODE == 1 ? fp16_scale_from_bits(D.maxbits[1]) : 1.0f;
+  const float sbs = MODE == 1 ? fp16_scale_from_bits(D.maxbits[0]) : 1.0f;
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = (wv / 4) * 64, wn0 = (wv % 4) * 64;
+  const int ll = lane % 16, lk = lane / 16;
+  const int lr = lane / 4;
+  const unsigned lchunk = (unsigned)((lane % 4) ^ ((lr >> 1) & 3));
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  // thread -> (grid point gl of the stage, complex column nn of the tile)
+  float2 rb[RB];
+  auto load_b = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = q * kBlockProj3 + threadIdx.x;
+      const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+      // out-of-range points and columns load an in-range value; store_b zeroes them
+      const long long g = min(g_begin + (long long)st * KG + gl, g_end - 1);
+      const int c = min(j0 / 2 + nn, no - 1);
+      rb[q] = U[g * no + c];
+    }
+  };
+  auto store_b = [&](int st, T* bh, T* bl) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = q * kBlockProj3 + threadIdx.x;
+      const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+      const bool ok = g_begin + (long long)st * KG + gl < g_end && j0 + 2 * nn < no2;
+      const float2 v = ok ? rb[q] : make_float2(0.f, 0.f);
+      T rh, rl, ih, il;
+      split2<MODE>(v.x, su, rh, rl);
+      split2<MODE>(v.y, su, ih, il);
+      const T nrh = (T)(-(float)rh), nrl = (T)(-(float)rl);
+      const int c0 = (2 * nn) * LK + 2 * gl, c1 = (2 * nn + 1) * LK + 2 * gl;
+      *(Pair<T>*)&bh[c0] = Pair<T>{rh, ih};
+      *(Pair<T>*)&bh[c1] = Pair<T>{ih, nrh};
+      *(Pair<T>*)&bl[c0] = Pair<T>{rl, il};
+      *(Pair<T>*)&bl[c1] = Pair<T>{il, nrl};
+    }
+  };
+  auto issue_a = [&](int st, T* ah, T* al) {
+    const unsigned kb = (unsigned)(kb0 + (long long)st * (2 * KK)) + 16u * lchunk;
+    const int ra = wv * 16;
+    const unsigned off = (unsigned)(ra + lr) * rowA + kb;
+    load_lds16(rah, (float*)(ah + ra * KK), off);
+    load_lds16(ral, (float*)(al + ra * KK), off);
+  };
+  auto compute = [&](const T* ah_s, const T* al_s, const T* bh_s, const T* bl_s) {
+    V8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm0 + i * 16 + ll;
+      const int o = r * KK + 8 * (lk ^ ((r >> 1) & 3));
+      ah[i] = *(const V8*)&ah_s[o];
+      al[i] = *(const V8*)&al_s[o];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int o = (wn0 + j * 16 + ll) * LK + 8 * lk;
+      bh[j] = *(const V8*)&bh_s[o];
+      bl[j] = *(const V8*)&bl_s[o];
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = Half<MODE>::mma(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = Half<MODE>::mma(al[i], bh[j], acc[i][j]);
+      }
+  };
+  issue_a(0, sA0h, sA0l);
+  load_b(0);
+  if (n_st > 1) issue_a(1, sA1h, sA1l);
+  store_b(0, sB0h, sB0l);
+  // stage ST reads A ring slot CA and B ring slot CB; it requests stage ST + 2
+  // into A slot NA and stores stage ST + 1 into B slot NB
+#define DCM_SYNC(MORE)                                                              \
+  do {                                                                              \
+    if (MORE)                                                                       \
+      __builtin_amdgcn_s_waitcnt(0x0072);   /* vmcnt(2) lgkmcnt(0) */               \
+    else                                                                            \
+      __builtin_amdgcn_s_waitcnt(0x0070);   /* vmcnt(0) lgkmcnt(0) */               \
+    asm volatile("" ::: "memory");                                                  \
+    __builtin_amdgcn_s_barrier();                                                   \
+    asm volatile("" ::: "memory");                                                  \
+  } while (0)
+#define DCM_PSTAGE_FULL(ST, CA, NA, CB, NB)                                         \
+  do {                                                                              \
+    DCM_SYNC(true);                                                                 \
+    load_b((ST) + 1);                                                               \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    issue_a((ST) + 2, sA##NA##h, sA##NA##l);                                        \
+    compute(sA##CA##h, sA##CA##l, sB##CB##h, sB##CB##l);                            \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    store_b((ST) + 1, sB##NB##h, sB##NB##l);                                        \
+  } while (0)
+#define DCM_PSTAGE_TAIL(ST, CA, NA, CB, NB)                                         \
+  do {                                                                              \
+    DCM_SYNC((ST) + 1 < n_st);                                                      \
+    if ((ST) + 1 < n_st) load_b((ST) + 1);                                          \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    if ((ST) + 2 < n_st) issue_a((ST) + 2, sA##NA##h, sA##NA##l);                   \
+    compute(sA##CA##h, sA##CA##l, sB##CB##h, sB##CB##l);                            \
+    __builtin_amdgcn_sched_barrier(0);                                              \
+    if ((ST) + 1 < n_st) store_b((ST) + 1, sB##NB##h, sB##NB##l);                   \
+  } while (0)
+  int st = 0;
+  for (; st + 7 < n_st; st += 6) {
+    DCM_PSTAGE_FULL(st, 0, 2, 0, 1);
+    DCM_PSTAGE_FULL(st + 1, 1, 0, 1, 0);
+    DCM_PSTAGE_FULL(st + 2, 2, 1, 0, 1);
+    DCM_PSTAGE_FULL(st + 3, 0, 2, 1, 0);
+    DCM_PSTAGE_FULL(st + 4, 1, 0, 0, 1);
+    DCM_PSTAGE_FULL(st + 5, 2, 1, 1, 0);
+  }
+  if (st < n_st) DCM_PSTAGE_TAIL(st, 0, 2, 0, 1);
+  if (st + 1 < n_st) DCM_PSTAGE_TAIL(st + 1, 1, 0, 1, 0);
+  if (st + 2 < n_st) DCM_PSTAGE_TAIL(st + 2, 2, 1, 0, 1);
+  if (st + 3 < n_st) DCM_PSTAGE_TAIL(st + 3, 0, 2, 1, 0);
+  if (st + 4 < n_st) DCM_PSTAGE_TAIL(st + 4, 1, 0, 0, 1);
+  if (st + 5 < n_st) DCM_PSTAGE_TAIL(st + 5, 2, 1, 1, 0);
+  if (st + 6 < n_st) DCM_PSTAGE_TAIL(st + 6, 0, 2, 0, 1);
+#undef DCM_PSTAGE_FULL
+#undef DCM_PSTAGE_TAIL
+#undef DCM_SYNC
+  const float unscale = 1.0f / (su * sbs);
+  float* __restrict__ part = (float*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + wm0 + i * 16 + 4 * lk + r;
+        const int jj = j0 + wn0 + j * 16 + ll;
+        if (p < np && jj < no2) part[(long long)p * no2 + jj] = acc[i][j][r] * unscale;
+      }
+}
+
 }  // namespace dcm
 

@@ -88,29 +88,32 @@ def test_split_correction_stage_counts(api, precision, mode, corr_variant):
         assert rel_fro(_np(hp[i]), ref) < 2e-6, i
 
 
-@pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
 def test_split_projection_variants_match_split_reference(api, precision, mode, proj_variant):
-    """Every projection tile variant (4: the projector planes loaded into LDS
-    directly) on two domains: 24 projectors / 21 orbitals (one partial tile)
-    and 136 projectors / 70 orbitals (a second tile in both dimensions with a
-    ragged edge); both grids end in a partial stage."""
+    """Every projection tile variant (4 and 5: the projector planes loaded
+    into LDS directly, two-stage on four waves and three-stage on eight) on
+    three domains: 24 projectors / 21 orbitals (one partial tile), 136
+    projectors / 70 orbitals (a second tile in both dimensions with a ragged
+    edge) and a 100-point grid (seven 16-point stages, fewer than one turn of
+    the unrolled ring); the larger grids end in partial stages."""
     import torch
-    doms = [_dom(), make_domain(52, (18, 17, 16), 70, 17, proj_per_atom=8, h=0.4, fd_order=4)]
+    doms = [_dom(), make_domain(52, (18, 17, 16), 70, 17, proj_per_atom=8, h=0.4, fd_order=4),
+            make_domain(54, (5, 5, 4), 9, 2, proj_per_atom=8, h=0.5, fd_order=2)]
     A = np.array([0.05, -0.11, 0.23])
     g = [to_device(d, precision) for d in doms]
     ws = api.Workspace.for_domains(g, precision)
     hp = [torch.empty_like(x.psi) for x in g]
     try:
         api.set_tuning("project", proj_variant)
-        api.density(g, a_tensor(np.stack([A, -A])), precision, ws, [dict(hpsi_occ=h) for h in hp],
+        api.density(g, a_tensor(np.stack([A, -A, A])), precision, ws, [dict(hpsi_occ=h) for h in hp],
                     a_per_domain=True)
         torch.cuda.synchronize()
     finally:
         api.set_tuning("project", -1)
     for i, dom in enumerate(doms):
         od = dom.rounded(np.float32)
-        a = A if i == 0 else -A
+        a = -A if i == 1 else A
         ref = (H.apply_hloc(od, a, od.psi) * od.occ[None, :]
                + S.apply_vnl_split(od, od.psi, mode, occ_scale=True))
         assert rel_fro(_np(hp[i]), ref) < 2e-6, i
