@@ -69,10 +69,16 @@ def main():
                     help="single: the 64^3 domain (default); batched: 512 uneven domains, graph-replayed")
     ap.add_argument("--graph-steps", type=int, default=100, help="steps captured per graph (batched)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--stream-ceiling", action="store_true",
+                    help="only measure what plain streams reach on this GPU (1 GiB operands: a read-only "
+                         "sum, a copy, and a two-read one-write add) and print one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 1 GiB buffer three times (reference dispatch "
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.stream_ceiling:
+        stream_ceiling()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: domains are independent, so a run over several GPUs "
               "would place whole domains (or orbital bands) on each and has no cross-GPU part to time.",
@@ -214,6 +220,37 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_2509_00966_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def stream_ceiling():
+    """Bandwidth that plain streams reach on this GPU, for reading the
+    stencil's HBM fraction: torch's own kernels on 1 GiB float32 operands,
+    best of five HIP-event-timed launches after a warm-up."""
+    import torch
+    dev = "cuda"
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.ones(n, dtype=torch.float32, device=dev)
+    o = torch.empty(n, dtype=torch.float32, device=dev)
+    s = torch.empty((), dtype=torch.float32, device=dev)
+    cases = {"read (sum)": (lambda: torch.sum(a, dim=0, out=s), 1),
+             "copy": (lambda: o.copy_(a), 2),
+             "2 reads + 1 write (add)": (lambda: torch.add(a, b, out=o), 3)}
+    res = {}
+    for name, (fn, k) in cases.items():
+        fn()
+        best = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        res[name] = {"ms": round(best, 4), "TB/s": round(k * 4.0 * n / best / 1e9, 3),
+                     "frac_of_8TBs": round(k * 4.0 * n / best / 1e9 / 8.0, 3)}
+    print(json.dumps({"stream_ceiling": res, "bytes_per_operand": 4 * n}))
 
 
 def measured_traffic(family, prec):
