@@ -163,17 +163,33 @@ int corr_variant(const dcmesh_domain& d, int prec) {
   }
   return base + wide_corr(d, prec);
 }
+// Padded output area of a tile grid over the n_proj x 2 n_orb projection,
+// relative to the useful area.
+double proj_waste(const dcmesh_domain& d, int bm, int bn) {
+  const double m = d.n_proj, n = 2.0 * d.n_orb;
+  return (double)(cdiv(d.n_proj, bm) * bm) * (double)(cdiv(2 * d.n_orb, bn) * bn) / (m * n);
+}
 int proj_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
-  // large tiles: the projector planes loaded into LDS directly, three stages
-  // on eight waves (proj_variant falls back to variant 0 where it cannot run)
-  if (is_split(prec)) return d.n_proj >= 96 ? 5 : 1;
-  const bool bigm = d.n_proj >= 96, bign = 2 * d.n_orb >= 96;
-  // large tiles: the three-product kernel with direct LDS loads where the rows
-  // allow it (proj_variant falls back to variant 0 otherwise)
-  return bigm ? (bign ? 4 : 1) : (bign ? 2 : 1);
+  // The cheapest of a few candidates by padded area times the kernel's time
+  // per useful flop without padding (relative; measured on the 64^3 domain and
+  // on batches of equal small domains).  FP32: 4 = the three-product kernel
+  // with direct LDS loads, 128 x 128 (proj_variant falls back to variant 0
+  // where it cannot run), 1 = 64 x 64, 2 = 64 x 128.  Split: 5 = three stages
+  // on eight waves, 128 x 256; 4 = two stages, 128 x 128; 1 = 64 x 64.
+  struct Cand { int v, bm, bn; double cost; };
+  static const Cand kF32[] = {{4, 128, 128, 1.0}, {1, 64, 64, 1.43}, {2, 64, 128, 1.36}};
+  static const Cand kSplit[] = {{5, 128, 256, 1.0}, {4, 128, 128, 1.15}, {1, 64, 64, 1.67}};
+  const Cand* c = is_split(prec) ? kSplit : kF32;
+  int best = c[0].v;
+  double best_cost = 1e300;
+  for (int k = 0; k < 3; ++k) {
+    const double cost = c[k].cost * proj_waste(d, c[k].bm, c[k].bn);
+    if (cost < best_cost) { best_cost = cost; best = c[k].v; }
+  }
+  return best;
 }
 int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
