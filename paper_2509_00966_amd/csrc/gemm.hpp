@@ -192,6 +192,34 @@ struct ReduceArgs {
   int unit_d;          // D = 1 (the reference-orbital projector of Eq. 5)
 };
 
+// Sum over the split-K partials of entry (p, n) of an np x n_orb complex
+// product: (re, im) of split s at ppart[s np 2 n_orb + p 2 n_orb + 2 n].  One
+// pair per load, eight splits in flight, summed in split order.
+template <typename TC>
+__device__ __forceinline__ void split_sum(const DomDesc& D, int np, int p, int n, TC& sr, TC& si) {
+  const long long no2 = 2LL * D.n_orb;
+  const TC* part = (const TC*)D.ppart + (long long)p * no2 + 2 * n;
+  const long long stride = (long long)np * no2;
+  sr = 0;
+  si = 0;
+  int s = 0;
+  for (; s + 8 <= D.n_split; s += 8) {
+    Vec<TC, 2> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = vload<TC, 2>(part + (s + u) * stride);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sr += v[u].v[0];
+      si += v[u].v[1];
+    }
+  }
+  for (; s < D.n_split; ++s) {
+    const Vec<TC, 2> v = vload<TC, 2>(part + s * stride);
+    sr += v.v[0];
+    si += v.v[1];
+  }
+}
+
 // Items: (dom, block index over n_proj * n_orb pairs).  Deterministic: the
 // split-K partials are summed in split order.  Q' rows are D.ldq apart.
 template <typename TC>
@@ -208,13 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DomDesc* __restrict__ d
   float qmax = 0.f;
   if (ok) {
     const int p = (int)(idx / no), n = (int)(idx % no);
-    const TC* part = (const TC*)D.ppart;
-    const long long stride = (long long)np * no2;
-    TC sr = 0, si = 0;
-    for (int s = 0; s < D.n_split; ++s) {
-      sr += part[s * stride + (long long)p * no2 + 2 * n];
-      si += part[s * stride + (long long)p * no2 + 2 * n + 1];
-    }
+    TC sr, si;
+    split_sum<TC>(D, np, p, n, sr, si);
     const double h3 = D.h * D.h * D.h;
     if (args.write_overlap) {
       D.overlap[((long long)p * no + n) * 2] = h3 * (double)sr;
@@ -273,13 +296,8 @@ __global__ __launch_bounds__(kBlock) void k_jnl_partial(const DomDesc* __restric
   double v = 0.0;
   if (idx < (long long)np * no) {
     const int p = (int)(idx / no), n = (int)(idx % no);
-    const TC* part = (const TC*)D.ppart;
-    const long long stride = (long long)np * no2;
-    TC sr = 0, si = 0;
-    for (int s = 0; s < D.n_split; ++s) {
-      sr += part[s * stride + (long long)p * no2 + 2 * n];
-      si += part[s * stride + (long long)p * no2 + 2 * n + 1];
-    }
+    TC sr, si;
+    split_sum<TC>(D, np, p, n, sr, si);
     const double h3 = D.h * D.h * D.h;
     const double rr = h3 * (double)sr, ri = h3 * (double)si;
     const TC* P = (const TC*)D.pmat;
