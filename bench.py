@@ -71,8 +71,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "split_bf16", "split_fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="single", choices=["single", "batched"],
-                    help="single: the 64^3 domain (default); batched: 512 uneven domains, graph-replayed")
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "adjoint"],
+                    help="single: the 64^3 domain (default); batched: 512 uneven domains, graph-replayed; "
+                         "adjoint: the pulse gradient on the 48^3 / 64-orbital domain")
     ap.add_argument("--graph-steps", type=int, default=100, help="steps captured per graph (batched)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--stream-ceiling", action="store_true",
@@ -97,6 +98,8 @@ def main():
 
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "adjoint":
+        return run_adjoint(args)
 
     log("bench: generating the 64^3 / 128-orbital / 512-projector domain")
     w = config(2)
@@ -283,6 +286,65 @@ def measured_traffic(family, prec):
             except ValueError:
                 return None
     return None
+
+
+def run_adjoint(args):
+    """Gradient of the absorbed energy with respect to 400 free A_z samples on
+    the 48^3 / 64-orbital / 256-projector domain (FD6, dt 0.02): 400 steps
+    forward with a checkpoint every 20, then the adjoint recursion backward with
+    each segment recomputed from its checkpoint.  ``--steps`` counts pulse
+    samples; one evaluation covers all 400, so the timed evaluations are
+    max(1, steps // 400).  Prints one JSON line."""
+    import torch
+    import paper_2509_00966_amd as api
+    from paper_2509_00966_amd.autograd import absorbed_energy
+    from synth import config
+    prec = args.precision
+    w = config(5)
+    dom = w.domains[0]
+    cd, rd = api.complex_dtype(prec), api.real_dtype(prec)
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dt)
+    g = api.Domain(dom.shape, dom.fd_order, dom.h, t(dom.psi, cd), t(dom.v_loc, rd), t(dom.proj, cd),
+                   t(dom.d, rd), t(dom.occ, rd))
+    ws = api.Workspace.for_domains([g], prec)
+    n = w.n_steps
+    az = w.a_mid[:, 2].copy()
+
+    def evaluate():
+        a = torch.from_numpy(az).to("cuda").requires_grad_(True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        loss = absorbed_energy(a, g, w.dt, prec, 20, ws)
+        e1.record()
+        loss.backward()
+        e2.record()
+        e2.synchronize()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2), loss.item(), a.grad
+
+    for _ in range(max(0, min(args.warmup, 1))):
+        evaluate()
+    reps = max(1, args.steps // n)
+    fw, bw = [], []
+    for _ in range(reps):
+        f, b, loss, grad = evaluate()
+        fw.append(f)
+        bw.append(b)
+    ms_eval = (sum(fw) + sum(bw)) / reps
+    out = {
+        "metric": "pulse-gradient orbital-gridpoint steps/s",
+        "value": dom.n_grid * dom.n_orb * n / (ms_eval * 1e-3),
+        "unit": "orbital-gridpoint steps/s (forward + adjoint per step)",
+        "n_gpus": 1, "steps": n * reps, "warmup": min(args.warmup, 1) * n,
+        "ms_per_step": ms_eval / n, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "fp32", "fp64": "f64", "split_bf16": "bf16x2+fp32", "split_fp16": "fp16x2+fp32"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "48^3 grid, h=0.4, 64 complex64 orbitals, 32 atoms x 8 projectors, FD6, "
+                               "400 free A_z samples, checkpoints every 20 steps, loss = absorbed energy",
+                   "precision": prec, "n_grid": dom.n_grid, "n_orb": dom.n_orb, "n_proj": dom.n_proj},
+        "forward_ms": sum(fw) / reps, "backward_ms": sum(bw) / reps,
+        "loss": loss, "grad_norm": float(grad.norm().item()), "grad_finite": bool(torch.isfinite(grad).all().item()),
+    }
+    print(json.dumps(out))
 
 
 def run_batched(args):
