@@ -351,9 +351,14 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
       const long long want = std::max<long long>(1, cdiv(256, std::max<long long>(1, stencil_blocks_xy)));
       D.zseg = (int)std::min<long long>(d.nz, std::max<long long>(16, cdiv(d.nz, want)));
     }
-    // split-K length depends on the domain alone, so a domain gives the same
-    // bits whether it runs alone or inside a batch
-    D.split_len = (int)std::min<long long>(2048, std::max<long long>(512, cdiv(cdiv(D.n_grid, 32), kProjKG) * kProjKG));
+    // split-K length depends on the domain alone (its sizes, not the tile
+    // variant), so a domain gives the same bits whether it runs alone or inside
+    // a batch: enough splits that the projection has about 512 blocks over
+    // nominal 128 x 128 tiles (and at least 32 splits), 512 to 2048 points each
+    const long long tiles = cdiv(D.n_proj, 128) * cdiv(2LL * D.n_orb, 128);
+    const long long want_splits = std::max<long long>(32, cdiv(512, std::max<long long>(1, tiles)));
+    D.split_len = (int)std::min<long long>(
+        2048, std::max<long long>(512, cdiv(cdiv(D.n_grid, want_splits), kProjKG) * kProjKG));
     D.n_split = (int)cdiv(D.n_grid, D.split_len);
     D.a_stride = 3;
     D.ldq = (2 * D.n_orb + 3) / 4 * 4;
