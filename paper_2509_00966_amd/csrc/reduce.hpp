@@ -113,41 +113,56 @@ __global__ __launch_bounds__(kBlock) void k_grad_partial(const DomDesc* __restri
   const double* A = D.a;
   const double ih = 1.0 / D.h;
   double acc[3] = {0, 0, 0};
-  for (int i = 0; i < EPT; ++i) {
-    const long long e = ((long long)it.a * EPT + i) * kBlock + threadIdx.x;
-    if (e >= total) break;
-    const long long g = e / no;
-    const int n = (int)(e - g * no);
-    const int x = (int)(g % nx), y = (int)((g / nx) % ny), z = (int)(g / ((long long)nx * ny));
-    const C m = mu[e], c = u[e];
-    // w = conj(mu) * coef
-    const double wr = (double)m.re * cre + (double)m.im * cim;
-    const double wi = (double)m.re * cim - (double)m.im * cre;
-    for (int d = 0; d < 3; ++d) {
-      double dr = 0, di = 0;
-      for (int k = 1; k <= r; ++k) {
-        long long gp, gm;
-        if (d == 0) {
-          gp = ((long long)z * ny + y) * nx + wrap(x + k, nx);
-          gm = ((long long)z * ny + y) * nx + wrap(x - k, nx);
-        } else if (d == 1) {
-          gp = ((long long)z * ny + wrap(y + k, ny)) * nx + x;
-          gm = ((long long)z * ny + wrap(y - k, ny)) * nx + x;
-        } else {
-          gp = ((long long)wrap(z + k, nz) * ny + y) * nx + x;
-          gm = ((long long)wrap(z - k, nz) * ny + y) * nx + x;
+  // I: the index type, 32-bit when the domain's element count allows it (a
+  // uniform branch per block; the divisions dominate the kernel otherwise)
+  auto run = [&](auto tag) {
+    using I = decltype(tag);
+    const I xy = (I)nx * (I)ny;
+    for (int i = 0; i < EPT; ++i) {
+      const long long e = ((long long)it.a * EPT + i) * kBlock + threadIdx.x;
+      if (e >= total) break;
+      const I ei = (I)e;
+      const I g = ei / (I)no;
+      const int n = (int)(ei - g * (I)no);
+      const int z = (int)(g / xy);
+      const I rem = g - (I)z * xy;
+      const int y = (int)(rem / (I)nx);
+      const int x = (int)(rem - (I)y * (I)nx);
+      const C m = mu[ei], c = u[ei];
+      // w = conj(mu) * coef
+      const double wr = (double)m.re * cre + (double)m.im * cim;
+      const double wi = (double)m.re * cim - (double)m.im * cre;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double dr = 0, di = 0;
+        for (int k = 1; k <= r; ++k) {
+          I gp, gm;
+          if (d == 0) {
+            gp = g - (I)x + (I)wrap(x + k, nx);
+            gm = g - (I)x + (I)wrap(x - k, nx);
+          } else if (d == 1) {
+            gp = g + ((I)wrap(y + k, ny) - (I)y) * (I)nx;
+            gm = g + ((I)wrap(y - k, ny) - (I)y) * (I)nx;
+          } else {
+            gp = g + ((I)wrap(z + k, nz) - (I)z) * xy;
+            gm = g + ((I)wrap(z - k, nz) - (I)z) * xy;
+          }
+          const C up = u[gp * (I)no + (I)n], um = u[gm * (I)no + (I)n];
+          const double ak = fd1(r, k) * ih;
+          dr += ak * ((double)up.re - um.re);
+          di += ak * ((double)up.im - um.im);
         }
-        const C up = u[gp * no + n], um = u[gm * no + n];
-        const double ak = fd1(r, k) * ih;
-        dr += ak * ((double)up.re - um.re);
-        di += ak * ((double)up.im - um.im);
+        // t = -i D1 u + A_d u
+        const double tr = di + A[d] * c.re;
+        const double ti = -dr + A[d] * c.im;
+        acc[d] += wr * tr - wi * ti;
       }
-      // t = -i D1 u + A_d u
-      const double tr = di + A[d] * c.re;
-      const double ti = -dr + A[d] * c.im;
-      acc[d] += wr * tr - wi * ti;
     }
-  }
+  };
+  if (total < (1LL << 31))
+    run(0u);
+  else
+    run(0LL);
   for (int d = 0; d < 3; ++d) {
     const double s = block_sum(acc[d], red);
     if (threadIdx.x == 0) D.g_part[(long long)(blockIdx.x - D.item0_elem) * 3 + d] = s;
