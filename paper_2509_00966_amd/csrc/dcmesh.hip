@@ -92,10 +92,10 @@ const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}, {128, 128}, {128, 256}};
 const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}, {64, 256}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
-// FP32 variant 4: the three-product kernel with the Q tile loaded into LDS
-// directly.  Split variants 4 and 5: both tiles loaded into LDS directly, on
-// four waves with two stages and on eight waves with three (other modes run
-// variant 5 as 4).
+// FP32 variants 4 and 5: the three-product kernel with the Q tile loaded into
+// LDS directly, on 128 and 64 complex columns.  Split variants 4 and 5: both
+// tiles loaded into LDS directly, on four waves with two stages and on eight
+// waves with three (FP64 runs variant 5 as 4).
 constexpr int kNCorr = 6;
 constexpr int kProjKG = 16;
 
@@ -165,6 +165,9 @@ int corr_variant(const dcmesh_domain& d, int prec) {
   int base = corr_variant_base(d, prec);
   if (base == 5) {
     if (is_split(prec)) return 5;
+    // FP32: the direct-LDS three-product kernel on 64 complex columns
+    // (launch keys 10 and 14); FP64 runs it as variant 4
+    if (prec == DCMESH_FP32) return direct_corr_ok(d, prec) ? (wide_corr(d, prec) ? 14 : 10) : 1 + wide_corr(d, prec);
     base = 4;
   }
   if (base == 4) {
@@ -208,9 +211,9 @@ int corr_variant_base(const dcmesh_domain& d, int prec) {
   // large tiles: both tiles loaded into LDS directly, three stages on eight waves
   if (is_split(prec)) return 2 * d.n_orb > 128 ? 5 : 1;
   const int n2 = 2 * d.n_orb;
-  // large tiles: the three-product kernel with the Q tile loaded into LDS
-  // directly (corr_variant falls back to variant 0 where it cannot run)
-  return n2 > 128 ? 4 : (n2 > 64 ? 1 : 2);
+  // the three-product kernel with the Q tile loaded into LDS directly, on 128
+  // or 64 complex columns (corr_variant falls back where it cannot run)
+  return n2 > 128 ? 4 : (n2 > 64 ? 5 : 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -409,7 +412,13 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_e_nl++;
   auto cv = [&](int i) { return doms[i].n_proj > 0 ? corr_variant(doms[i], prec) : -1; };
   group_launch(P.corr, P.items, n_dom, cv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kCorrF64[cv(i) % 4] : is_split(prec) ? kCorrSplit[cv(i)] : kCorrF32[cv(i) % 4];
+    // FP32 launch keys 8 and 12: the direct-LDS kernel on the tile of variant
+    // 0; keys 10 and 14: on 64 complex columns
+    const int v = cv(i);
+    const GemmVariant t = is_fp64(prec)  ? kCorrF64[v % 4]
+                          : is_split(prec) ? kCorrSplit[v]
+                          : (v == 10 || v == 14) ? GemmVariant{64, 128}
+                                                 : kCorrF32[v % 4];
     const DomDesc& D = P.desc[i];
     for (long long gt = 0; gt < cdiv(D.n_grid, t.bm); ++gt)
       for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, (int)gt, nt, 0});
@@ -804,6 +813,8 @@ void launch_correct(const Ctx& c, int out_slot) {
         case 6: k_correct<T, T, 64, 64, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 7: k_correct<T, T, 128, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 8: k_correct3m_dl<64, 128, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 10: k_correct3m_dl<64, 64, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 14: k_correct3m_dl<64, 64, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         default: k_correct3m_dl<64, 128, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       }
     } else {

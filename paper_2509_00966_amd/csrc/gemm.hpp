@@ -828,19 +828,20 @@ __global__ __launch_bounds__(kBlock) void k_correct3m(const DomDesc* __restrict_
 // The three-product correction with the Q tile moved from memory straight
 // into LDS (buffer loads with an LDS destination) and both tiles
 // double-buffered (one barrier per stage).  A stage holds KC projectors: the
-// three Q planes give 3 KC rows of BNC floats (512 B; one wave instruction
-// moves two rows), and the projector rows of B are staged through registers
-// into padded LDS rows as in k_correct3m.  Odd Q rows are stored rotated by 16
-// floats, so the two 16-lane halves that read consecutive rows use disjoint
-// LDS banks.  Each plane's buffer ends after n_proj rows, so rows past it read
+// three Q planes give 3 KC rows of BNC floats (BNC = 128: 512 B, one wave
+// instruction moves two rows; BNC = 64: 256 B, four rows), and the projector
+// rows of B are staged through registers into padded LDS rows as in
+// k_correct3m.  Odd Q rows are stored rotated by 16 floats, so the two 16-lane
+// quarters of a half-wave, which read consecutive rows, use disjoint LDS banks.  Each plane's buffer ends after n_proj rows, so rows past it read
 // as zero; columns past n_orb reach only outputs that are not stored.
 template <int BMG, int BNC, int KC, int VW>
 __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restrict__ doms,
                                                          const Item* __restrict__ items, int out_slot) {
   constexpr int TM = BMG / 32, TN = BNC / 32;
   constexpr int LA = 2 * KC + 2;
-  static_assert(BNC == 128, "Q rows of 512 B");
-  static_assert(KC % 2 == 0, "Q rows move in pairs");
+  static_assert(BNC == 128 || BNC == 64, "Q rows of 512 B or 256 B");
+  constexpr int RPI = 256 / BNC;                                 // Q rows per wave instruction (1 KB)
+  static_assert(KC % RPI == 0, "Q rows move in whole instructions");
   constexpr int VA = BMG * 2 * KC / VW;
   constexpr int RA = (VA + kBlock - 1) / kBlock;
   constexpr int SB = 3 * KC * BNC;
@@ -866,9 +867,12 @@ __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restri
   const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int wm0 = (wv / 2) * (BMG / 2), wn0 = (wv % 2) * (BNC / 2);
   const int ll = lane % 16, lk = lane / 16;
-  // lanes 0-31 move an even row, 32-63 the next (odd) row rotated by 16 floats
-  const int qt = lane % 32;
-  const unsigned qcol = 4u * (unsigned)(n0 + 4 * (lane < 32 ? qt : (qt + 4) % 32));
+  // one instruction moves RPI consecutive rows (BNC / 4 lanes each); odd rows
+  // are stored rotated by 16 floats
+  constexpr int LPR = BNC / 4;                                   // lanes per row
+  static_assert(LPR * RPI == kWave, "one wave instruction moves RPI whole rows");
+  const int qt = lane % LPR, qodd = (lane / LPR) & 1;
+  const unsigned qcol = 4u * (unsigned)(n0 + 4 * (qodd ? (qt + 4) % LPR : qt));
   const int bshift = (lk & 1) ? 16 : 0;                          // this lane reads odd rows
   f32x4 k1[TM][TN], k2[TM][TN], k3[TM][TN];
 #pragma unroll
@@ -901,12 +905,12 @@ __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restri
     }
   };
   auto issue_q = [&](int st, float* sB) {
-    // row pairs (plane, 2m), (plane, 2m + 1): 3 KC / 2 instructions per stage
+    // row groups (plane, RPI m .. RPI m + RPI - 1): 3 KC / RPI instructions per stage
 #pragma unroll
-    for (int pr = wv; pr < 3 * KC / 2; pr += 4) {
-      const int pl = pr / (KC / 2), m = pr % (KC / 2);
-      const int row = st * KC + 2 * m + lane / 32;
-      load_lds16(rq[pl], sB + (pl * KC + 2 * m) * BNC, (unsigned)row * qrow + qcol);
+    for (int pr = wv; pr < 3 * KC / RPI; pr += 4) {
+      const int pl = pr / (KC / RPI), m = pr % (KC / RPI);
+      const int row = st * KC + RPI * m + lane / LPR;
+      load_lds16(rq[pl], sB + (pl * KC + RPI * m) * BNC, (unsigned)row * qrow + qcol);
     }
   };
   auto compute = [&](const float* sA, const float* sB) {
