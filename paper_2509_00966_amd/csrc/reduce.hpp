@@ -6,6 +6,8 @@
 // bitwise reproducible.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace dcm {
@@ -115,8 +117,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_partial(const DomDesc* __restri
   double acc[3] = {0, 0, 0};
   // I: the index type, 32-bit when the domain's element count allows it (a
   // uniform branch per block; the divisions dominate the kernel otherwise)
-  auto run = [&](auto tag) {
+  auto run = [&](auto tag, auto rc) {
     using I = decltype(tag);
+    constexpr int R = decltype(rc)::value;   // the stencil radius, so the neighbour loads unroll
     const I xy = (I)nx * (I)ny;
     for (int i = 0; i < EPT; ++i) {
       const long long e = ((long long)it.a * EPT + i) * kBlock + threadIdx.x;
@@ -135,7 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_partial(const DomDesc* __restri
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         double dr = 0, di = 0;
-        for (int k = 1; k <= r; ++k) {
+#pragma unroll
+        for (int k = 1; k <= R; ++k) {
           I gp, gm;
           if (d == 0) {
             gp = g - (I)x + (I)wrap(x + k, nx);
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_partial(const DomDesc* __restri
             gm = g + ((I)wrap(z - k, nz) - (I)z) * xy;
           }
           const C up = u[gp * (I)no + (I)n], um = u[gm * (I)no + (I)n];
-          const double ak = fd1(r, k) * ih;
+          const double ak = fd1(R, k) * ih;
           dr += ak * ((double)up.re - um.re);
           di += ak * ((double)up.im - um.im);
         }
@@ -159,10 +163,18 @@ __global__ __launch_bounds__(kBlock) void k_grad_partial(const DomDesc* __restri
       }
     }
   };
+  auto by_radius = [&](auto tag) {
+    if (r == 1)
+      run(tag, std::integral_constant<int, 1>{});
+    else if (r == 2)
+      run(tag, std::integral_constant<int, 2>{});
+    else
+      run(tag, std::integral_constant<int, 3>{});
+  };
   if (total < (1LL << 31))
-    run(0u);
+    by_radius(0u);
   else
-    run(0LL);
+    by_radius(0LL);
   for (int d = 0; d < 3; ++d) {
     const double s = block_sum(acc[d], red);
     if (threadIdx.x == 0) D.g_part[(long long)(blockIdx.x - D.item0_elem) * 3 + d] = s;
