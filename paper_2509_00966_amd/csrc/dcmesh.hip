@@ -211,9 +211,10 @@ int corr_variant_base(const dcmesh_domain& d, int prec) {
   // large tiles: both tiles loaded into LDS directly, three stages on eight waves
   if (is_split(prec)) return 2 * d.n_orb > 128 ? 5 : 1;
   const int n2 = 2 * d.n_orb;
-  // the three-product kernel with the Q tile loaded into LDS directly, on 128
-  // or 64 complex columns (corr_variant falls back where it cannot run)
-  return n2 > 128 ? 4 : (n2 > 64 ? 5 : 2);
+  // the three-product kernel with the Q tile loaded into LDS directly on 64
+  // complex columns: never more padding than the 128-column tile, and three
+  // waves per SIMD instead of two (corr_variant falls back where it cannot run)
+  return n2 > 64 ? 5 : 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -420,8 +421,12 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
                           : (v == 10 || v == 14) ? GemmVariant{64, 128}
                                                  : kCorrF32[v % 4];
     const DomDesc& D = P.desc[i];
+    const size_t b0 = it.size();
+    const int nnt = (int)cdiv(2 * D.n_orb, t.bn);
     for (long long gt = 0; gt < cdiv(D.n_grid, t.bm); ++gt)
-      for (int nt = 0; nt < cdiv(2 * D.n_orb, t.bn); ++nt) it.push_back({i, (int)gt, nt, 0});
+      for (int nt = 0; nt < nnt; ++nt) it.push_back({i, (int)gt, nt, 0});
+    // the column tiles of a row block share its B rows: one XCD, one L2
+    if (nnt > 1) xcd_interleave(it, b0, it.size(), (size_t)nnt);
   });
   group_launch(P.dens, P.items, n_dom, [](int) { return 0; },
                [&](int i, std::vector<Item>& it) {
