@@ -81,10 +81,10 @@ struct GemmVariant { int bm, bn; };
 // in complex orbitals is half the real-column tile listed here.
 const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
-// FP32 variant 4: the three-product kernel with direct LDS loads.  Split
-// variants 4 and 5: the projector planes loaded into LDS directly, on four
-// waves with two stages and on eight waves with three (other modes run
-// variant 5 as 4).
+// FP32 variants 4 and 5: the three-product kernel with direct LDS loads on
+// 128 and 64 projectors.  Split variants 4 and 5: the projector planes loaded
+// into LDS directly, on four waves with two stages and on eight waves with
+// three (FP64 runs variant 5 as 4).
 constexpr int kNProj = 6;
 constexpr int kProjDirect = 8; // its launch key
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
@@ -147,6 +147,9 @@ int proj_variant(const dcmesh_domain& d, int prec) {
   int base = proj_variant_base(d, prec);
   if (base == 5) {
     if (is_split(prec)) return direct_split_proj_ok(d) ? 5 : 0;
+    // FP32: the three-product kernel with direct LDS loads on 64 projectors
+    // (launch key kProjDirect + 1); FP64 runs it as variant 4
+    if (prec == DCMESH_FP32) return direct_proj_ok(d, prec) ? kProjDirect + 1 : 1 + wide_proj(d, prec);
     base = 4;
   }
   if (base == 4) {
@@ -188,17 +191,18 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
   // The cheapest of a few candidates by padded area times the kernel's time
   // per useful flop without padding (relative; measured on the 64^3 domain and
-  // on batches of equal small domains).  FP32: 4 = the three-product kernel
-  // with direct LDS loads, 128 x 128 (proj_variant falls back to variant 0
-  // where it cannot run), 1 = 64 x 64, 2 = 64 x 128.  Split: 5 = three stages
+  // on batches of equal small domains).  FP32: 4 and 5 = the three-product
+  // kernel with direct LDS loads, 128 x 128 and 64 x 128 (proj_variant falls
+  // back where it cannot run), 1 = 64 x 64, 2 = 64 x 128.  Split: 5 = three stages
   // on eight waves, 128 x 256; 4 = two stages, 128 x 128; 1 = 64 x 64.
   struct Cand { int v, bm, bn; double cost; };
-  static const Cand kF32[] = {{4, 128, 128, 1.0}, {1, 64, 64, 1.43}, {2, 64, 128, 1.36}};
+  static const Cand kF32[] = {{4, 128, 128, 1.0}, {5, 64, 128, 1.01}, {1, 64, 64, 1.43}, {2, 64, 128, 1.36}};
   static const Cand kSplit[] = {{5, 128, 256, 1.0}, {4, 128, 128, 1.15}, {1, 64, 64, 1.67}};
   const Cand* c = is_split(prec) ? kSplit : kF32;
+  const int nc = is_split(prec) ? 3 : 4;
   int best = c[0].v;
   double best_cost = 1e300;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < nc; ++k) {
     const double cost = c[k].cost * proj_waste(d, c[k].bm, c[k].bn);
     if (cost < best_cost) { best_cost = cost; best = c[k].v; }
   }
@@ -394,7 +398,12 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
 
   auto pv = [&](int i) { return doms[i].n_proj > 0 ? proj_variant(doms[i], prec) : -1; };
   group_launch(P.proj, P.items, n_dom, pv, [&](int i, std::vector<Item>& it) {
-    const GemmVariant t = is_fp64(prec) ? kProjF64[pv(i) % 4] : is_split(prec) ? kProjSplit[pv(i)] : kProjF32[pv(i) % 4];
+    // FP32 launch key kProjDirect + 1: the direct-LDS kernel on 64 projectors x 64 complex orbitals
+    const int v = pv(i);
+    const GemmVariant t = is_fp64(prec)  ? kProjF64[v % 4]
+                          : is_split(prec) ? kProjSplit[v]
+                          : v == kProjDirect + 1 ? GemmVariant{64, 128}
+                                                 : kProjF32[v % 4];
     const DomDesc& D = P.desc[i];
     const size_t b0 = it.size();
     const int nmt = (int)cdiv(D.n_proj, t.bm), nnt = (int)cdiv(2 * D.n_orb, t.bn);
@@ -780,6 +789,7 @@ void launch_project(const Ctx& c, int u_slot, int a_slot = -1) {
         case 5: k_project<T, T, 64, 64, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 6: k_project<T, T, 64, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 7: k_project<T, T, 128, 256, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 9: k_project3m_dl<64, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         default: k_project3m_dl<128, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
       }
     } else {

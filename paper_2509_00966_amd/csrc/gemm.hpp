@@ -587,7 +587,10 @@ __global__ __launch_bounds__(kBlock) void k_project3m_dl(const DomDesc* __restri
                                                          const Item* __restrict__ items, ProjArgs args) {
   constexpr int TM = BM / 32, TN = BNC / 32;
   constexpr int RA = 2 * BM, RB = 2 * BNC;             // floats per LDS row
-  static_assert(RA == 256 && RB == 128, "rows of 1 KB (B) and 512 B (u)");
+  // one wave instruction moves 1 KB: RPA rows of B (LPA lanes each), RPB of u
+  constexpr int RPA = 256 / RA, LPA = RA / 4, RPB = 256 / RB, LPB = RB / 4;
+  static_assert((RA == 256 || RA == 128) && RB == 128, "rows of 1 KB or 512 B (B) and 512 B (u)");
+  static_assert(RPA * LPA == kWave && RPB * LPB == kWave, "whole rows per wave instruction");
   static_assert(KG % 8 == 0, "whole wave instructions per stage");
   constexpr int SA = KG * RA, SB = KG * RB;
   __shared__ __align__(16) float sA0[SA], sA1[SA];
@@ -609,8 +612,8 @@ __global__ __launch_bounds__(kBlock) void k_project3m_dl(const DomDesc* __restri
   const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int wm0 = (wv / 2) * (BM / 2), wn0 = (wv % 2) * (BNC / 2);
   const int ll = lane % 16, lk = lane / 16;
-  const unsigned colA = 4u * (2u * p0 + 4u * lane);              // this lane's 16 bytes of a B row
-  const unsigned colB = 4u * (2u * n0 + 4u * (lane % 32));       // ... of a u row
+  const unsigned colA = 4u * (2u * p0 + 4u * (lane % LPA));      // this lane's 16 bytes of a B row
+  const unsigned colB = 4u * (2u * n0 + 4u * (lane % LPB));      // ... of a u row
   f32x4 k1[TM][TN], k2[TM][TN], k3[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -619,10 +622,11 @@ __global__ __launch_bounds__(kBlock) void k_project3m_dl(const DomDesc* __restri
 
   auto issue = [&](int st, float* sA, float* sB) {
 #pragma unroll
-    for (int r = wv; r < KG; r += 4) load_lds16(ra, sA + r * RA, (unsigned)(st * KG + r) * rowA + colA);
+    for (int r = wv; r < KG / RPA; r += 4)
+      load_lds16(ra, sA + RPA * r * RA, (unsigned)(st * KG + RPA * r + lane / LPA) * rowA + colA);
 #pragma unroll
-    for (int r2 = wv; r2 < KG / 2; r2 += 4)
-      load_lds16(rb, sB + 2 * r2 * RB, (unsigned)(st * KG + 2 * r2 + lane / 32) * rowB + colB);
+    for (int r2 = wv; r2 < KG / RPB; r2 += 4)
+      load_lds16(rb, sB + RPB * r2 * RB, (unsigned)(st * KG + RPB * r2 + lane / LPB) * rowB + colB);
   };
   auto compute = [&](const float* sA, const float* sB) {
 #pragma unroll 2

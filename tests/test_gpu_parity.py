@@ -318,11 +318,12 @@ def test_every_z_segment_choice_matches_oracle(api, zseg):
                                                 ((16, 16, 16), 64, 8),      # whole stages, 64 projectors
                                                 ((17, 15, 9), 21, 2),       # odd N_o
                                                 ((12, 11, 10), 130, 3)])    # two orbital tiles
-@pytest.mark.parametrize("family,variant", [("project", 4), ("correct", 4), ("correct", 5)])
+@pytest.mark.parametrize("family,variant", [("project", 4), ("project", 5), ("correct", 4), ("correct", 5)])
 def test_direct_lds_products_match_oracle(api, family, variant, shape, n_orb, n_atoms):
     """The FP32 projection / correction with tiles loaded straight into LDS
-    (tuning variant 4 of each family; correction variant 5: the same on 64
-    complex columns), two steps against the oracle."""
+    (tuning variant 4 of each family; variant 5: the projection on 64
+    projectors, the correction on 64 complex columns), two steps against the
+    oracle."""
     torch = _torch()
     dom = make_domain(43, shape, n_orb, n_atoms, proj_per_atom=8, h=0.4, fd_order=6)
     a_mid = _field(2)
