@@ -143,6 +143,12 @@ def main():
     bytes_stencil = ng * no * (16.0 + 3 * 24.0) / 4 + ng * 4.0
     bytes_gemm = ng * npj * 8.0 + ng * no * 8.0   # projectors once (FP32 or hi+lo 16-bit), orbitals once
     roofline, kernels = roofline_of(prof, flops_gemm, bytes_stencil, prec, bytes_gemm)
+    if "stencil" in kernels and "achieved" in kernels["stencil"]:
+        # the stencil reads two arrays and writes one: also report it against
+        # what a plain two-read one-write stream reaches on this GPU
+        st = stream_rates(cases=("2 reads + 1 write (add)",))["2 reads + 1 write (add)"]
+        kernels["stencil"]["stream_2r1w_GBs"] = st["TB/s"] * 1e3
+        kernels["stencil"]["frac_of_stream"] = kernels["stencil"]["achieved"] / (st["TB/s"] * 1e3)
 
     finite = bool(torch.isfinite(g.psi).all().item())
     if args.copy_calibration:
@@ -232,6 +238,11 @@ def kernel_source_hash():
 
 
 def stream_ceiling():
+    """Print stream_rates() of every case as one JSON line."""
+    print(json.dumps({"stream_ceiling": stream_rates(), "bytes_per_operand": 4 << 28}))
+
+
+def stream_rates(cases=None):
     """Bandwidth that plain streams reach on this GPU, for reading the
     stencil's HBM fraction: torch's own kernels on 1 GiB float32 operands,
     best of five HIP-event-timed launches after a warm-up."""
@@ -242,11 +253,13 @@ def stream_ceiling():
     b = torch.ones(n, dtype=torch.float32, device=dev)
     o = torch.empty(n, dtype=torch.float32, device=dev)
     s = torch.empty((), dtype=torch.float32, device=dev)
-    cases = {"read (sum)": (lambda: torch.sum(a, dim=0, out=s), 1),
-             "copy": (lambda: o.copy_(a), 2),
-             "2 reads + 1 write (add)": (lambda: torch.add(a, b, out=o), 3)}
+    all_cases = {"read (sum)": (lambda: torch.sum(a, dim=0, out=s), 1),
+                 "copy": (lambda: o.copy_(a), 2),
+                 "2 reads + 1 write (add)": (lambda: torch.add(a, b, out=o), 3)}
     res = {}
-    for name, (fn, k) in cases.items():
+    for name, (fn, k) in all_cases.items():
+        if cases is not None and name not in cases:
+            continue
         fn()
         best = None
         for _ in range(5):
@@ -259,7 +272,7 @@ def stream_ceiling():
             best = ms if best is None else min(best, ms)
         res[name] = {"ms": round(best, 4), "TB/s": round(k * 4.0 * n / best / 1e9, 3),
                      "frac_of_8TBs": round(k * 4.0 * n / best / 1e9 / 8.0, 3)}
-    print(json.dumps({"stream_ceiling": res, "bytes_per_operand": 4 * n}))
+    return res
 
 
 def measured_traffic(family, prec):
