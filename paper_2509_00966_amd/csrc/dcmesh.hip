@@ -82,14 +82,15 @@ struct GemmVariant { int bm, bn; };
 const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
 // FP32 variants 4 and 5: the three-product kernel with direct LDS loads on
-// 128 and 64 projectors.  Split variants 4 and 5: the projector planes loaded
-// into LDS directly, on four waves with two stages and on eight waves with
-// three (FP64 runs variant 5 as 4).
-constexpr int kNProj = 6;
+// 128 and 64 projectors.  Split variants 4, 5 and 6: the projector planes
+// loaded into LDS directly, on four waves with two stages (128 x 128), on
+// eight waves with three (128 x 256), and on four waves with two stages
+// (64 x 64).  Other modes run variants 5 and 6 as 4 (FP64) or 5 and 4 (FP32).
+constexpr int kNProj = 7;
 constexpr int kProjDirect = 8; // its launch key
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 // split-precision kernels (variant 2 of each stages twice as much per LDS pass)
-const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}, {128, 128}, {128, 256}};
+const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}, {128, 128}, {128, 256}, {64, 64}};
 const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}, {64, 256}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
 // FP32 variants 4 and 5: the three-product kernel with the Q tile loaded into
@@ -145,6 +146,10 @@ bool direct_split_proj_ok(const dcmesh_domain& d) {
 }
 int proj_variant(const dcmesh_domain& d, int prec) {
   int base = proj_variant_base(d, prec);
+  if (base == 6) {
+    if (is_split(prec)) return direct_split_proj_ok(d) ? 6 : 1;
+    base = 4;
+  }
   if (base == 5) {
     if (is_split(prec)) return direct_split_proj_ok(d) ? 5 : 0;
     // FP32: the three-product kernel with direct LDS loads on 64 projectors
@@ -194,10 +199,10 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   // on batches of equal small domains).  FP32: 4 and 5 = the three-product
   // kernel with direct LDS loads, 128 x 128 and 64 x 128 (proj_variant falls
   // back where it cannot run), 1 = 64 x 64, 2 = 64 x 128.  Split: 5 = three stages
-  // on eight waves, 128 x 256; 4 = two stages, 128 x 128; 1 = 64 x 64.
+  // on eight waves, 128 x 256; 4 and 6 = two stages, 128 x 128 and 64 x 64.
   struct Cand { int v, bm, bn; double cost; };
   static const Cand kF32[] = {{4, 128, 128, 1.0}, {5, 64, 128, 1.01}, {1, 64, 64, 1.43}, {2, 64, 128, 1.36}};
-  static const Cand kSplit[] = {{5, 128, 256, 1.0}, {4, 128, 128, 1.15}, {1, 64, 64, 1.67}};
+  static const Cand kSplit[] = {{5, 128, 256, 1.0}, {4, 128, 128, 1.15}, {6, 64, 64, 1.59}};
   const Cand* c = is_split(prec) ? kSplit : kF32;
   const int nc = is_split(prec) ? 3 : 4;
   int best = c[0].v;
@@ -884,6 +889,7 @@ void launch_project_split(const Ctx& c, int u_slot) {
       case 2: k_project_split<MODE, 128, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 3: k_project_split<MODE, 128, 256, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 4: k_project_split_dl<MODE, 128, 128><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      case 6: k_project_split_dl<MODE, 64, 64><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       default: k_project_split_dl3<MODE><<<g, dim3(kBlockProj3), 0, c.s>>>(c.d_desc, it, u_slot); break;
     }
   }

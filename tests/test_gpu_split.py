@@ -88,11 +88,12 @@ def test_split_correction_stage_counts(api, precision, mode, corr_variant):
         assert rel_fro(_np(hp[i]), ref) < 2e-6, i
 
 
-@pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
 def test_split_projection_variants_match_split_reference(api, precision, mode, proj_variant):
-    """Every projection tile variant (4 and 5: the projector planes loaded
-    into LDS directly, two-stage on four waves and three-stage on eight) on
+    """Every projection tile variant (4, 5 and 6: the projector planes loaded
+    into LDS directly, two-stage 128 x 128, three-stage 128 x 256, two-stage
+    64 x 64) on
     three domains: 24 projectors / 21 orbitals (one partial tile), 136
     projectors / 70 orbitals (a second tile in both dimensions with a ragged
     edge) and a 100-point grid (seven 16-point stages, fewer than one turn of
