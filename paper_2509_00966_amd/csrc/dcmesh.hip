@@ -871,9 +871,11 @@ void launch_presplit(const Ctx& c) {
   }
 }
 
+// umax_known (FP16): maxbits[1] already holds max |u| of every domain,
+// gathered by the correction that wrote u
 template <int MODE>
-void launch_project_split(const Ctx& c, int u_slot) {
-  if (MODE == 1) {
+void launch_project_split(const Ctx& c, int u_slot, bool umax_known = false) {
+  if (MODE == 1 && !umax_known) {
     ProfScope prof_(DCMESH_FAM_SPLIT, c.s);
     launch_zero_maxbits(c, 1);
     for (const Launch& L : c.P->absmax_u)
@@ -895,8 +897,13 @@ void launch_project_split(const Ctx& c, int u_slot) {
   }
 }
 
+// umax (FP16): the correction kernels also gather max |out| into maxbits[1]
+// (cleared here; the projection that read it was launched before), the scale
+// source of the next projection when out is its input
 template <int MODE>
-void launch_correct_split(const Ctx& c, int out_slot) {
+void launch_correct_split(const Ctx& c, int out_slot, bool umax = false) {
+  const int um = (MODE == 1 && umax) ? 1 : 0;
+  if (um) launch_zero_maxbits(c, 1);
   {
     ProfScope prof_(DCMESH_FAM_SPLIT, c.s);
     for (const Launch& L : c.P->splitq) k_split_q<MODE><<<L.count, kBlock, 0, c.s>>>(c.d_desc, c.d_items + L.first);
@@ -906,28 +913,33 @@ void launch_correct_split(const Ctx& c, int out_slot) {
     const Item* it = c.d_items + L.first;
     const dim3 g(L.count), b(kBlock);
     switch (L.variant) {
-      case 0: k_correct_split<MODE, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      case 1: k_correct_split<MODE, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      case 2: k_correct_split<MODE, 64, 256, 64><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      case 3: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      case 4: k_correct_split_dl<MODE, 64, 256><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
-      default: k_correct_split_dl3<MODE><<<g, dim3(kBlockCorr3), 0, c.s>>>(c.d_desc, it, out_slot); break;
+      case 0: k_correct_split<MODE, 64, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
+      case 1: k_correct_split<MODE, 64, 128, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
+      case 2: k_correct_split<MODE, 64, 256, 64><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
+      case 3: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
+      case 4: k_correct_split_dl<MODE, 64, 256><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
+      default: k_correct_split_dl3<MODE><<<g, dim3(kBlockCorr3), 0, c.s>>>(c.d_desc, it, out_slot, um); break;
     }
   }
 }
 
 // out = base + coef * f^occ * H(A_step) u   (full H: local sweep, then the
 // projector correction added in place).
+// fp16_scale (FP16 mode): bit 0 = maxbits[1] already holds max |u| (the
+// correction that wrote u gathered it), bit 1 = gather max |out| for the next
+// stage
+constexpr int kScaleKnown = 1, kScaleGather = 2;
 template <typename T>
 void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double cre, double cim,
-                 int occ_scale, int step, int want_energy, int want_density = 0, bool nonlocal = true) {
+                 int occ_scale, int step, int want_energy, int want_density = 0, bool nonlocal = true,
+                 int fp16_scale = 0) {
   const int prec = c.P->prec;
   const bool nl = nonlocal && c.P->any_proj;
   if (nl) {
     if (prec == DCMESH_SPLIT_BF16) {
       launch_project_split<0>(c, u_slot);
     } else if (prec == DCMESH_SPLIT_FP16) {
-      launch_project_split<1>(c, u_slot);
+      launch_project_split<1>(c, u_slot, (fp16_scale & kScaleKnown) != 0);
       launch_zero_maxbits(c, 2);
     } else {
       launch_project<T>(c, u_slot);
@@ -940,7 +952,7 @@ void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double c
     if (prec == DCMESH_SPLIT_BF16)
       launch_correct_split<0>(c, out_slot);
     else if (prec == DCMESH_SPLIT_FP16)
-      launch_correct_split<1>(c, out_slot);
+      launch_correct_split<1>(c, out_slot, (fp16_scale & kScaleGather) != 0);
     else
       launch_correct<T>(c, out_slot);
   }
@@ -1087,11 +1099,16 @@ int run_step_eq2(CallSetup& cs, int32_t n_steps, double dt, double v_nl) {
 template <typename T>
 void one_step(const Ctx& c, int k, double dt, bool want_rho_j, bool want_e) {
   // stage 4 applies H to psi_k: it also yields E_k and the rho/j partials of psi_k
-  apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0, want_rho_j ? 1 : 0);
+  // FP16 scales: every correction gathers max |out|, the input of the next
+  // stage (of the next step, for the last); from the second step of a call on,
+  // psi's max is the one the previous step's last correction gathered
+  const int first = (k > 0 ? kScaleKnown : 0) | kScaleGather, next = kScaleKnown | kScaleGather;
+  apply_stage<T>(c, SLOT_PSI, SLOT_PSI, SLOT_B0, 0.0, -dt / 4, 0, k, want_e ? 1 : 0, want_rho_j ? 1 : 0, true,
+                 first);
   if (want_rho_j) launch_density_finish<T>(c, k, k);
-  apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, k, 0);
-  apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B0, 0.0, -dt / 2, 0, k, 0);
-  apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_PSI, 0.0, -dt, 0, k, 0);
+  apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_B1, 0.0, -dt / 3, 0, k, 0, 0, true, next);
+  apply_stage<T>(c, SLOT_B1, SLOT_PSI, SLOT_B0, 0.0, -dt / 2, 0, k, 0, 0, true, next);
+  apply_stage<T>(c, SLOT_B0, SLOT_PSI, SLOT_PSI, 0.0, -dt, 0, k, 0, 0, true, next);
   if (want_e) launch_energy<T>(c, k);
 }
 

@@ -323,11 +323,25 @@ __global__ __launch_bounds__(kBlock) void k_split_q(const DomDesc* __restrict__ 
   ((T*)D.qt_lo)[idx] = lo;
 }
 
+// FP16 mode: the max |x| of the values a wave has written into maxbits[1],
+// the scale source of the next projection, whose input they are (an atomic max
+// on the float bits, skipped where the stored value is already as large).
+// Every lane of the wave calls it.
+__device__ __forceinline__ void wave_umax(const DomDesc& D, float m) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    unsigned* dst = &D.maxbits[1];
+    const unsigned bits = __float_as_uint(m);
+    if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, bits);
+  }
+}
+
 // out[g][j] += sum_k Bs[g][k] Qt[j][k] (hi*hi + hi*lo + lo*hi), unscaled.
 // Items: (dom, g tile, j tile).  KC reduction indices per LDS stage.
 template <int MODE, int BMG, int BN, int KC>
 __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restrict__ doms,
-                                                          const Item* __restrict__ items, int out_slot) {
+                                                          const Item* __restrict__ items, int out_slot, int umax) {
   using T = typename Half<MODE>::T;
   using V8 = typename Half<MODE>::V8;
   constexpr int LK = KC + 8;
@@ -442,6 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
   // out += acc: every read is issued before the first write, so the reads
   // overlap instead of each waiting behind the previous write
   float prev[TM][TN][4];
+  float vmax = 0.f;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -460,8 +475,13 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
       for (int r = 0; r < 4; ++r) {
         const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
         const int jj = j0 + wn0 + j * 16 + ll;
-        if (g < D.n_grid && jj < no2) out[g * no2 + jj] = prev[i][j][r] + acc[i][j][r] * unscale;
+        if (g < D.n_grid && jj < no2) {
+          const float v = prev[i][j][r] + acc[i][j][r] * unscale;
+          out[g * no2 + jj] = v;
+          vmax = fmaxf(vmax, fabsf(v));
+        }
       }
+  if (MODE == 1 && umax) wave_umax(D, vmax);
 }
 
 // The split correction with both pre-split operands moved from memory
@@ -475,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_correct_split(const DomDesc* __restr
 // as zero and reach only outputs that are not stored.
 template <int MODE, int BMG, int BN>
 __global__ __launch_bounds__(kBlock) void k_correct_split_dl(const DomDesc* __restrict__ doms,
-                                                             const Item* __restrict__ items, int out_slot) {
+                                                             const Item* __restrict__ items, int out_slot, int umax) {
   using T = typename Half<MODE>::T;
   using V8 = typename Half<MODE>::V8;
   constexpr int KC = 32;
@@ -571,6 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_correct_split_dl(const DomDesc* __re
   const float unscale = MODE == 1 ? 1.0f / (fp16_scale_from_bits(D.maxbits[0]) * fp16_scale_from_bits(D.maxbits[2]))
                                   : 1.0f;
   // out += acc, one 16-row tile at a time (reads before writes)
+  float vmax = 0.f;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     float prev[TN][4];
@@ -588,9 +609,14 @@ __global__ __launch_bounds__(kBlock) void k_correct_split_dl(const DomDesc* __re
       for (int r = 0; r < 4; ++r) {
         const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
         const int jj = j0 + wn0 + j * 16 + ll;
-        if (g < D.n_grid && jj < no2) out[g * no2 + jj] = prev[j][r] + acc[i][j][r] * unscale;
+        if (g < D.n_grid && jj < no2) {
+          const float v = prev[j][r] + acc[i][j][r] * unscale;
+          out[g * no2 + jj] = v;
+          vmax = fmaxf(vmax, fabsf(v));
+        }
       }
   }
+  if (MODE == 1 && umax) wave_umax(D, vmax);
 }
 
 // The split correction on eight waves with a three-deep ring of LDS stages:
@@ -603,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_correct_split_dl(const DomDesc* __re
 constexpr int kBlockCorr3 = 512;
 template <int MODE>
 __global__ __launch_bounds__(kBlockCorr3) void k_correct_split_dl3(const DomDesc* __restrict__ doms,
-                                                                   const Item* __restrict__ items, int out_slot) {
+                                                                   const Item* __restrict__ items, int out_slot, int umax) {
   using T = typename Half<MODE>::T;
   using V8 = typename Half<MODE>::V8;
   constexpr int BMG = 128, BN = 256, KC = 32, NW = kBlockCorr3 / kWave;
@@ -749,6 +775,7 @@ __global__ __launch_bounds__(kBlockCorr3) void k_correct_split_dl3(const DomDesc
 #undef DCM_SYNC
   const float unscale = MODE == 1 ? 1.0f / (fp16_scale_from_bits(D.maxbits[0]) * fp16_scale_from_bits(D.maxbits[2]))
                                   : 1.0f;
+  float vmax = 0.f;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     float prev[TN][4];
@@ -766,9 +793,14 @@ __global__ __launch_bounds__(kBlockCorr3) void k_correct_split_dl3(const DomDesc
       for (int r = 0; r < 4; ++r) {
         const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
         const int jj = j0 + wn0 + j * 16 + ll;
-        if (g < D.n_grid && jj < no2) out[g * no2 + jj] = prev[j][r] + acc[i][j][r] * unscale;
+        if (g < D.n_grid && jj < no2) {
+          const float v = prev[j][r] + acc[i][j][r] * unscale;
+          out[g * no2 + jj] = v;
+          vmax = fmaxf(vmax, fabsf(v));
+        }
       }
   }
+  if (MODE == 1 && umax) wave_umax(D, vmax);
 }
 
 // The split projection with the pre-split projector planes Bt moved from
