@@ -15,4 +15,5 @@ from .workloads import (  # noqa: F401
     config,
     batched_domain_shapes,
     batched_domain,
+    batched_subset,
 )

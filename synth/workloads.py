@@ -276,6 +276,22 @@ def batched_domain(index: int, n_domains: int = 512, seed: int = 4) -> Domain:
                        fd_order=6, rng=rng)
 
 
+def batched_subset(count: int = 16, seed: int = 404, n_domains: int = 512):
+    """Indices of the seeded subset of the batched workload used for parity
+    checks and the CPU baseline: the smallest and the largest domain (by
+    N_g N_o N_p), then seeded picks until ``count``."""
+    shapes = batched_domain_shapes(n_domains)
+    size = np.array([n ** 3 * no * (8 * na) for n, no, na in shapes])
+    pick = [int(size.argmin()), int(size.argmax())]
+    rng = np.random.default_rng(seed)
+    for i in rng.permutation(len(shapes)):
+        if len(pick) == count:
+            break
+        if int(i) not in pick:
+            pick.append(int(i))
+    return pick
+
+
 # --------------------------------------------------------------------------
 # the five named workloads
 # --------------------------------------------------------------------------

@@ -40,7 +40,8 @@ def _loss_grad(api, dom, az, dt, precision, ckpt):
     return loss.item(), a.grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision,ckpt", [("fp64", 4), ("fp64", 12), ("fp32", 5), ("split_bf16", 5)])
+@pytest.mark.parametrize("precision,ckpt", [("fp64", 4), ("fp64", 12), ("fp32", 5), ("split_bf16", 5),
+                                            ("split_fp16", 5)])
 def test_gradient_matches_oracle(api, precision, ckpt):
     dom = make_domain(71, (16, 17, 18), 6, 2, proj_per_atom=8, h=0.4, fd_order=6)
     n, dt = 12, 0.05
@@ -55,10 +56,17 @@ def test_gradient_matches_oracle(api, precision, ckpt):
     # energy's scale; the gradient is compared directly.
     from oracle import observables as O
     e_scale = abs(O.energy(od, np.zeros(3), od.psi))
-    tol_l = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-5}[precision]
-    tol_g = {"fp64": 1e-10, "fp32": 1e-4, "split_bf16": 1e-3}[precision]
-    assert abs(loss - l_ref) <= tol_l * e_scale
-    assert np.linalg.norm(grad - g_ref[:, 2]) <= tol_g * np.linalg.norm(g_ref[:, 2])
+    # FP16 hi+lo keeps 22 significant bits against FP32's 24: four times the
+    # FP32 bounds.  Its forward chunks take the FP16 scale from the
+    # corrections, the one-step recompute searches for it: the recompute check
+    # inside backward needs both to give the same bits.
+    tol_l = {"fp64": 1e-12, "fp32": 1e-6, "split_bf16": 1e-5, "split_fp16": 4e-6}[precision]
+    tol_g = {"fp64": 1e-10, "fp32": 1e-4, "split_bf16": 1e-3, "split_fp16": 4e-4}[precision]
+    el = abs(loss - l_ref) / e_scale
+    eg = np.linalg.norm(grad - g_ref[:, 2]) / np.linalg.norm(g_ref[:, 2])
+    print(f"[parity] {precision}: loss error {el:.2e} of the energy scale, gradient error {eg:.2e}")
+    assert el <= tol_l
+    assert eg <= tol_g
 
 
 def test_reduced_gradient_workload_fp32_vs_oracle(api):

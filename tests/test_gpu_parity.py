@@ -3,12 +3,15 @@ inputs, at sizes that span several tiles of every kernel and leave ragged
 tails (grid edges, orbital chunks, projector and orbital GEMM tiles).
 
 Tolerances: FP64 path <= 1e-11 relative (rounding order only); FP32 path
-<= 1e-5 relative on psi (the FP32 bar after 100 steps), tighter per operator.
+<= 1e-5 relative on psi (the FP32 bar after 100 steps).  The FP32 H psi is
+held to 2 U32 kappa per error view, kappa the condition number of the
+operator's sum of terms (helpers.fp32_operator_tol); the other FP32
+operators (density, current, adjoint) to multiples of 2e-6.
 """
 import numpy as np
 import pytest
 
-from helpers import a_tensor, oracle_inputs, rel_fro, to_device
+from helpers import a_tensor, assert_close, fp32_operator_tol, oracle_inputs, to_device
 from oracle import adjoint as ADJ
 from oracle import hamiltonian as H
 from oracle import observables as O
@@ -17,7 +20,7 @@ from synth import config, make_domain, pulse_midpoints
 
 pytestmark = pytest.mark.gpu
 
-TOL_OP = {"fp64": 1e-12, "fp32": 5e-6}
+TOL_OP = {"fp64": 1e-12, "fp32": 2e-6}
 TOL_PSI = {"fp64": 1e-11, "fp32": 1e-5}
 
 
@@ -63,7 +66,8 @@ def test_hpsi_matches_oracle(api, precision, order):
     torch.cuda.synchronize()
     od = oracle_inputs(dom, precision)
     ref = O.occupied_h(od, A, od.psi)
-    assert rel_fro(_np(hp), ref) < TOL_OP[precision]
+    tol = TOL_OP["fp64"] if precision == "fp64" else fp32_operator_tol(od, A, od.psi, ref)
+    assert_close(_np(hp), ref, tol)
     e_ref = O.energy(od, A, od.psi)
     assert abs(e.item() - e_ref) < TOL_OP[precision] * 10 * abs(e_ref)
 
@@ -80,7 +84,7 @@ def test_step_matches_oracle(api, precision):
     torch.cuda.synchronize()
     od = oracle_inputs(dom, precision)
     ref, _ = P.propagate(od, a_mid, dt, od.psi)
-    assert rel_fro(_np(g.psi), ref) < TOL_PSI[precision]
+    assert_close(_np(g.psi), ref, TOL_PSI[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -101,10 +105,10 @@ def test_per_step_observables(api, precision):
     od = oracle_inputs(dom, precision)
     ref, ro = P.propagate(od, a_mid, dt, od.psi, want_rho=True, want_j=True, want_energy=True)
     tol = TOL_OP[precision] * 5
-    assert rel_fro(_np(obs["rho"]), ro["rho"]) < tol
-    assert rel_fro(_np(obs["j"]), ro["j"]) < tol * 5
+    assert_close(_np(obs["rho"]), ro["rho"], tol, orbitals=False)
+    assert_close(_np(obs["j"]), ro["j"], tol * 5, orbitals=False)
     assert np.abs(_np(obs["energy"]) - ro["energy"]).max() < tol * np.abs(ro["energy"]).max()
-    assert rel_fro(_np(g.psi), ref) < TOL_PSI[precision]
+    assert_close(_np(g.psi), ref, TOL_PSI[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -121,8 +125,8 @@ def test_density_current_overlap(api, precision):
     api.density([g], a_tensor(A[None]), precision, ws, [out])
     torch.cuda.synchronize()
     od = oracle_inputs(dom, precision)
-    assert rel_fro(_np(out["rho"]), O.density(od, od.psi)) < TOL_OP[precision]
-    assert rel_fro(_np(out["j"]), O.current(od, A, od.psi)) < TOL_OP[precision] * 10
+    assert_close(_np(out["rho"]), O.density(od, od.psi), TOL_OP[precision], orbitals=False)
+    assert_close(_np(out["j"]), O.current(od, A, od.psi), TOL_OP[precision] * 10, orbitals=False)
     s = _np(out["overlap"])
     s = s[..., 0] + 1j * s[..., 1]
     # the overlap is accumulated in FP64 from the (rounded) inputs: tight in both modes
@@ -146,7 +150,7 @@ def test_adjoint_step_matches_oracle(api, precision):
     od = oracle_inputs(dom, precision)
     lam_in = lam.astype(np.complex64).astype(np.complex128) if precision == "fp32" else lam
     lam_ref, g_ref = ADJ.adjoint_step(od, A, dt, od.psi, lam_in)
-    assert rel_fro(_np(lam_d), lam_ref) < TOL_OP[precision] * 5
+    assert_close(_np(lam_d), lam_ref, TOL_OP[precision] * 5)
     assert np.abs(_np(grad) - g_ref).max() < TOL_OP[precision] * 50 * np.abs(g_ref).max()
 
 
@@ -161,7 +165,7 @@ def test_config1_full_run_fp64(api):
     api.step([g], a_tensor(w.a_mid), w.dt, n, "fp64", ws, obs=[obs])
     torch.cuda.synchronize()
     ref, ro = P.propagate(dom, w.a_mid, w.dt, dom.psi, want_energy=True)
-    assert rel_fro(_np(g.psi), ref) < 1e-12
+    assert_close(_np(g.psi), ref, 1e-12)
     assert np.abs(_np(obs["energy"]) - ro["energy"]).max() < 1e-12 * np.abs(ro["energy"]).max()
 
 
@@ -176,7 +180,7 @@ def test_no_projectors(api):
     api.step([g], a_tensor(a_mid), 0.02, 3, "fp64", ws)
     torch.cuda.synchronize()
     ref, _ = P.propagate(dom, a_mid, 0.02, dom.psi)
-    assert rel_fro(_np(g.psi), ref) < 1e-11
+    assert_close(_np(g.psi), ref, 1e-11)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -200,7 +204,7 @@ def test_batched_equals_single_domains(api, precision):
         assert torch.equal(gb.psi, g1.psi)
         od = oracle_inputs(d, precision)
         ref, _ = P.propagate(od, a_mid, 0.02, od.psi)
-        assert rel_fro(_np(gb.psi), ref) < TOL_PSI[precision]
+        assert_close(_np(gb.psi), ref, TOL_PSI[precision])
 
 
 def test_graph_replay_equals_eager_bitwise(api):
@@ -253,7 +257,7 @@ def test_tile_variants_agree(api, variant):
     finally:
         for fam in ("stencil", "project", "correct"):
             api.set_tuning(fam, -1)
-    assert rel_fro(_np(g.psi), ref) < TOL_PSI["fp32"]
+    assert_close(_np(g.psi), ref, TOL_PSI["fp32"])
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -285,9 +289,9 @@ def test_every_stencil_variant_matches_oracle(api, variant, order, precision):
     finally:
         api.set_tuning("stencil", -1)
     tol = TOL_PSI[precision]
-    assert rel_fro(_np(g.psi), ref) < tol
-    assert rel_fro(_np(rho), obs["rho"]) < tol
-    assert rel_fro(_np(j), obs["j"]) < tol * 10
+    assert_close(_np(g.psi), ref, tol)
+    assert_close(_np(rho), obs["rho"], tol, orbitals=False)
+    assert_close(_np(j), obs["j"], tol * 10, orbitals=False)
     assert np.abs(_np(e) - obs["energy"]).max() < tol * np.abs(obs["energy"]).max()
 
 
@@ -311,7 +315,7 @@ def test_every_z_segment_choice_matches_oracle(api, zseg):
         finally:
             api.set_tuning("zseg", -1)
             api.set_tuning("stencil", -1)
-        assert rel_fro(_np(g.psi), ref) < TOL_PSI["fp32"], variant
+        assert_close(_np(g.psi), ref, TOL_PSI["fp32"], label=str(variant))
 
 
 @pytest.mark.parametrize("shape,n_orb,n_atoms", [((19, 13, 21), 22, 3),     # N_g tail, 24 projectors
@@ -337,7 +341,7 @@ def test_direct_lds_products_match_oracle(api, family, variant, shape, n_orb, n_
         torch.cuda.synchronize()
     finally:
         api.set_tuning(family, -1)
-    assert rel_fro(_np(g.psi), ref) < TOL_PSI["fp32"]
+    assert_close(_np(g.psi), ref, TOL_PSI["fp32"])
 
 
 def test_check_finite_flags_nan(api):
