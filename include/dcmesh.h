@@ -32,11 +32,18 @@
  * contents are private to the library between calls.  The library keeps no
  * device pointer after a call returns, except inside a graph handle.
  *
+ * Work lists: each call copies its domain descriptors and tile lists into the
+ * head of the workspace from pinned host memory that the library keeps
+ * between calls, one buffer per distinct table content (at most 64 idle ones
+ * are kept).  A call whose tables are not staged yet allocates such a buffer
+ * (hipHostMalloc) and an event; nothing else is allocated.
+ *
  * Streams: all work is queued on the given stream (a hipStream_t passed as
  * void*, NULL = the default stream) and calls return without waiting for it.
- * No entry point synchronises, allocates or reads device memory on the host
- * unless DCMESH_FLAG_CHECK_FINITE is set, so the calls can be captured into a
- * HIP graph.
+ * No entry point synchronises or reads device memory on the host unless
+ * DCMESH_FLAG_CHECK_FINITE is set.  A call made under stream capture must find
+ * its tables staged (the allocation above is not allowed there):
+ * dcmesh_graph_create stages them before it captures.
  *
  * Errors: each entry point returns a DCMESH_* status; 0 means success.  All
  * arguments are validated on the host before any HIP call, so an invalid
@@ -129,7 +136,8 @@ typedef struct dcmesh_density_out {
   double* overlap;
 } dcmesh_density_out;
 
-/* Workspace needed by every entry point below (one size serves all, except
+/* Not in the paper (the caller-owned scratch of the calls below).
+ * Workspace needed by every entry point below (one size serves all, except
  * dcmesh_step_eq2: DCMESH_FLAG_EQ2) for these domains and precision.  Host-only; writes
  * *bytes.  Workspace pointers must be 256-byte aligned. */
 int dcmesh_workspace_bytes(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
@@ -164,7 +172,11 @@ int dcmesh_step_eq2(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
                     void* work, size_t work_bytes, uint32_t flags, void* stream);
 
 /* Observables of the current orbitals for the field a_dev ([n_a][3], float64,
- * device).  out: host array [n_dom]. */
+ * device): the density and current that couple the orbitals to the field
+ * (Sec. V.B.5), the energy E = h^3 sum_n f_n <psi_n|H|psi_n> of Eq. 3's H, its
+ * adjoint seed f_n H psi_n, and the FP64 overlap S = h^3 Psi^H Psi (the
+ * orthonormality check; Sec. V.B.5's overlap product).  out: host array
+ * [n_dom]. */
 int dcmesh_density(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
                    const double* a_dev, int32_t a_per_domain,
                    const dcmesh_density_out* out,
@@ -230,7 +242,9 @@ int dcmesh_step_maxwell(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
                         double dt, int32_t n_steps, double* field, double* a_mid, double* current,
                         void* work, size_t work_bytes, uint32_t flags, void* stream);
 
-/* One step of the adjoint recursion for the gradient of a loss L(psi_N):
+/* Not in the paper: the pulse-gradient extension (the gradient of an
+ * absorbed energy with respect to the vector-potential samples).
+ * One step of the adjoint recursion for the gradient of a loss L(psi_N):
  *     lambda_k = U_k^H lambda_{k+1} = T4(+i dt H(A_k)) lambda_{k+1}
  *     grad[d] += 2 Re <lambda_{k+1}, (dU_k/dA_d) psi_k>,  dH/dA_d = -i D1_d + A_d
  * doms[i].psi holds psi_k (read only).  lambda: host array [n_dom] of device
@@ -241,7 +255,8 @@ int dcmesh_adjoint_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
                         double dt, double* grad_dev,
                         void* work, size_t work_bytes, uint32_t flags, void* stream);
 
-/* Record the work of one dcmesh_step call (same arguments) into a HIP graph
+/* Not in the paper (launch plumbing for many steps of many domains).
+ * Record the work of one dcmesh_step call (same arguments) into a HIP graph
  * owned by the returned handle; replay it with dcmesh_graph_launch.  The
  * handle keeps the pointers it was built with. */
 int dcmesh_graph_create(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
@@ -252,7 +267,8 @@ int dcmesh_graph_create(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
 int dcmesh_graph_launch(void* graph, void* stream);
 int dcmesh_graph_destroy(void* graph);
 
-/* Tile choices: dcmesh_set_tuning selects a kernel variant for a kernel family
+/* Not in the paper (tile plumbing).
+ * Tile choices: dcmesh_set_tuning selects a kernel variant for a kernel family
  * (DCMESH_KERNEL_*) and value (see dcmesh_tuning_options); -1 restores the
  * built-in heuristic.  Process-wide; takes effect for calls made afterwards.
  * DCMESH_KERNEL_ZSEG picks the z-segment length of the stencil sweep (0: from
@@ -263,13 +279,25 @@ enum dcmesh_kernel { DCMESH_KERNEL_STENCIL = 0, DCMESH_KERNEL_PROJECT = 1, DCMES
 int dcmesh_set_tuning(int32_t kernel, int32_t variant);
 int dcmesh_tuning_options(int32_t kernel, int32_t* count);
 
-/* Waits for the events recorded by calls made with DCMESH_FLAG_PROFILE (since
+/* Per-shape tile choices, the table an autotuner fills (not in the paper):
+ * domains of exactly shape's nx, ny, nz, fd_order, n_orb and n_proj (its
+ * pointers are not read) in this precision use this variant of the kernel
+ * family (values as dcmesh_set_tuning; the z segment is not per shape);
+ * -1 removes the entry.  A global dcmesh_set_tuning choice takes precedence;
+ * shapes without an entry use the built-in rules.  Process-wide; for calls
+ * made afterwards.  dcmesh_clear_tuning_shapes empties the table. */
+int dcmesh_set_tuning_shape(int32_t kernel, int32_t precision, const dcmesh_domain* shape, int32_t variant);
+int dcmesh_clear_tuning_shapes(void);
+
+/* Not in the paper (measurement plumbing).
+ * Waits for the events recorded by calls made with DCMESH_FLAG_PROFILE (since
  * the last collect), and writes per family the summed kernel time in ms and
  * the number of launches.  total_ms and launches: host arrays of n entries
  * (n <= DCMESH_N_FAMILIES).  Synchronises with the recorded events. */
 int dcmesh_profile_collect(double* total_ms, int64_t* launches, int32_t n);
 
-/* Message for the calling thread's last failed call ("" if none). */
+/* Not in the paper.  Message for the calling thread's last failed call ("" if
+ * none). */
 const char* dcmesh_last_error(void);
 
 #ifdef __cplusplus

@@ -17,6 +17,8 @@ from .api import (  # noqa: F401
     set_tuning,
     step,
     step_eq2,
+    set_tuning_shape,
+    clear_tuning_shapes,
     step_maxwell,
     tuning_options,
     workspace_bytes,

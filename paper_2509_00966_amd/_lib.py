@@ -28,7 +28,7 @@ EXPORTS = (
     "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_step_eq2", "dcmesh_density", "dcmesh_occupations",
     "dcmesh_current", "dcmesh_step_maxwell", "dcmesh_adjoint_step",
     "dcmesh_graph_create", "dcmesh_graph_launch", "dcmesh_graph_destroy",
-    "dcmesh_set_tuning", "dcmesh_tuning_options", "dcmesh_profile_collect", "dcmesh_last_error",
+    "dcmesh_set_tuning", "dcmesh_tuning_options", "dcmesh_set_tuning_shape", "dcmesh_clear_tuning_shapes", "dcmesh_profile_collect", "dcmesh_last_error",
 )
 
 
@@ -80,6 +80,8 @@ def _load():
         "dcmesh_graph_destroy": [P],
         "dcmesh_set_tuning": [I32, I32],
         "dcmesh_tuning_options": [I32, ctypes.POINTER(I32)],
+        "dcmesh_set_tuning_shape": [I32, I32, dom_p, I32],
+        "dcmesh_clear_tuning_shapes": [],
         "dcmesh_profile_collect": [ctypes.POINTER(D), ctypes.POINTER(I64), I32],
     }
     for name, args in sig.items():

@@ -141,7 +141,8 @@ def step(domains: Sequence[Domain], a: torch.Tensor, dt: float, n_steps: int, pr
 
 
 def step_eq2(domains: Sequence[Domain], psi0: Sequence[torch.Tensor], v_nl: float, a: torch.Tensor, dt: float,
-             n_steps: int, precision: str, work: Workspace, a_per_domain: bool = False, stream=None):
+             n_steps: int, precision: str, work: Workspace, a_per_domain: bool = False, profile: bool = False,
+             stream=None):
     """Eq. 2 steps with the reference-orbital nonlocal operator of Eq. 5 (see
     dcmesh_step_eq2); psi0: per-domain reference orbitals like psi."""
     arr = _doms(domains, precision)
@@ -150,12 +151,12 @@ def step_eq2(domains: Sequence[Domain], psi0: Sequence[torch.Tensor], v_nl: floa
             raise ValueError("psi0 must match psi in dtype, shape and be contiguous")
     pp = (ctypes.c_void_p * len(psi0))(*[p.data_ptr() for p in psi0])
     check(lib.dcmesh_step_eq2(arr, len(domains), PRECISION[precision], pp, float(v_nl), a.data_ptr(),
-                              int(a_per_domain), a.shape[-2], float(dt), int(n_steps), work.ptr, work.nbytes, 0,
-                              _stream(stream)))
+                              int(a_per_domain), a.shape[-2], float(dt), int(n_steps), work.ptr, work.nbytes,
+                              _lib.FLAG_PROFILE if profile else 0, _stream(stream)))
 
 
 def density(domains: Sequence[Domain], a: torch.Tensor, precision: str, work: Workspace,
-            outs: List[dict], a_per_domain: bool = False, stream=None):
+            outs: List[dict], a_per_domain: bool = False, profile: bool = False, stream=None):
     """Observables of the current orbitals.  ``outs``: per-domain dict with any
     of 'rho', 'j', 'energy' (float64 [1]), 'hpsi_occ', 'overlap' (float64
     [N_o, N_o, 2])."""
@@ -164,7 +165,8 @@ def density(domains: Sequence[Domain], a: torch.Tensor, precision: str, work: Wo
         DcmeshDensityOut(_ptr(x.get("rho")), _ptr(x.get("j")), _ptr(x.get("energy")), _ptr(x.get("hpsi_occ")),
                          _ptr(x.get("overlap"))) for x in outs])
     check(lib.dcmesh_density(arr, len(domains), PRECISION[precision], a.data_ptr(), int(a_per_domain), o,
-                             work.ptr, work.nbytes, 0, _stream(stream)))
+                             work.ptr, work.nbytes,
+                             _lib.FLAG_PROFILE if profile else 0, _stream(stream)))
 
 
 def occupations(domains: Sequence[Domain], psi0: Sequence[torch.Tensor], precision: str, work: Workspace,
@@ -301,6 +303,19 @@ def profile_collect() -> dict:
 
 def set_tuning(kernel: str, variant: int):
     check(lib.dcmesh_set_tuning(_lib.KERNEL[kernel], int(variant)))
+
+
+def set_tuning_shape(kernel: str, precision: str, shape: tuple, fd_order: int, n_orb: int, n_proj: int,
+                     variant: int):
+    """Variant of a kernel family for domains of exactly this shape ((nx, ny,
+    nz), fd_order, n_orb, n_proj) in this precision; -1 removes the entry."""
+    nx, ny, nz = shape
+    d = DcmeshDomain(nx, ny, nz, fd_order, n_orb, n_proj, 0.0, None, None, None, None, None)
+    check(lib.dcmesh_set_tuning_shape(_lib.KERNEL[kernel], PRECISION[precision], ctypes.byref(d), int(variant)))
+
+
+def clear_tuning_shapes():
+    check(lib.dcmesh_clear_tuning_shapes())
 
 
 def tuning_options(kernel: str) -> int:

@@ -7,9 +7,21 @@ orbitals, and the fastest variant per family is kept.  Results are cached in
 a JSON file keyed by the domain shapes, the precision and the GPU architecture,
 so a later run reuses them without timing.
 
+Two granularities:
+
+* ``tune`` / ``apply``: one variant per family for the whole call (a global
+  choice);
+* ``tune_classes`` / ``apply_classes``: the domains are grouped into shape
+  classes (grid edge and orbital count ranges), each class is timed on its
+  own domains, and the winners go into the library's per-shape table
+  (``dcmesh_set_tuning_shape``), so every domain runs the variant tuned for
+  its class.
+
     from paper_2509_00966_amd import autotune
     best = autotune.tune(domains, a, dt, "fp32")      # {"stencil": v, "project": v, "correct": v}
     autotune.apply(best)
+    table = autotune.tune_classes(domains, a, dt, "fp32")
+    autotune.apply_classes(domains, "fp32", table)
 """
 from __future__ import annotations
 
@@ -86,3 +98,56 @@ def tune(domains, a, dt, precision, cache_path: str = DEFAULT_CACHE, steps=2, fo
     with open(cache_path, "w") as f:
         json.dump(cache, f, indent=1)
     return best
+
+
+EDGE_BINS = (20, 27, 34, 41)            # grid edges [20, 27), [27, 34), [34, 41)
+ORB_BINS = (1, 17, 33, 49, 65, 81, 97)  # orbital counts in ranges of 16
+
+
+def shape_class(d, edge_bins=EDGE_BINS, orb_bins=ORB_BINS):
+    """(fd_order, edge range, orbital range) of a domain; shapes outside the
+    ranges get their own open-ended class."""
+    import bisect
+    return (d.fd_order, bisect.bisect_right(edge_bins, max(d.shape)), bisect.bisect_right(orb_bins, d.n_orb))
+
+
+def tune_classes(domains, a, dt, precision, cache_path: str = DEFAULT_CACHE, steps=2, force=False):
+    """{class: {family: variant}}: each shape class's fastest variants, timed
+    on that class's domains alone."""
+    key = _key(domains, precision) + ":classes"
+    cache = _load(cache_path)
+    if key in cache and not force:
+        return {tuple(json.loads(k)): v for k, v in cache[key]["table"].items()}
+    groups = {}
+    for i, d in enumerate(domains):
+        groups.setdefault(shape_class(d), []).append(i)
+    work = api.Workspace.for_domains(domains, precision)
+    table, times = {}, {}
+    for cls, idx in sorted(groups.items()):
+        t = time_variants([domains[i] for i in idx], a, dt, precision, steps, work=work)
+        table[cls] = {fam: min(tf, key=tf.get) for fam, tf in t.items()}
+        times[cls] = t
+    cache = _load(cache_path)
+    cache[key] = {"table": {json.dumps(list(c)): v for c, v in table.items()},
+                  "ms": {json.dumps(list(c)): {f: {str(k): x for k, x in tf.items()} for f, tf in t.items()}
+                         for c, t in times.items()}}
+    os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
+    with open(cache_path, "w") as f:
+        json.dump(cache, f, indent=1)
+    return table
+
+
+def apply_classes(domains, precision, table):
+    """Fill the library's per-shape table: every domain's shape gets its
+    class's variants."""
+    for d in domains:
+        best = table.get(shape_class(d))
+        if best is None:
+            continue
+        for fam in FAMILIES:
+            if fam in best:
+                api.set_tuning_shape(fam, precision, tuple(d.shape), d.fd_order, d.n_orb, d.n_proj, int(best[fam]))
+
+
+def reset_classes():
+    api.clear_tuning_shapes()

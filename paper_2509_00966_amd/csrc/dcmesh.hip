@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -82,11 +83,13 @@ struct GemmVariant { int bm, bn; };
 const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
 // FP32 variants 4 and 5: the three-product kernel with direct LDS loads on
-// 128 and 64 projectors.  Split variants 4, 5 and 6: the projector planes
-// loaded into LDS directly, on four waves with two stages (128 x 128), on
-// eight waves with three (128 x 256), and on four waves with two stages
-// (64 x 64).  Other modes run variants 5 and 6 as 4 (FP64) or 5 and 4 (FP32).
-constexpr int kNProj = 7;
+// 128 and 64 projectors; variant 7: the three-product kernel through
+// registers on 64 projectors x 32 complex orbitals (any row length).  Split
+// variants 4, 5 and 6: the projector planes loaded into LDS directly, on four
+// waves with two stages (128 x 128), on eight waves with three (128 x 256),
+// and on four waves with two stages (64 x 64).  Other modes run variants 5
+// and 6 as 4 (FP64) or 5 and 4 (FP32), and 7 as 1 (FP64) or 6 (split).
+constexpr int kNProj = 8;
 constexpr int kProjDirect = 8; // its launch key
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 // split-precision kernels (variant 2 of each stages twice as much per LDS pass)
@@ -94,13 +97,35 @@ const GemmVariant kProjSplit[] = {{128, 128}, {64, 64}, {128, 128}, {128, 256}, 
 const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}, {64, 256}, {128, 256}};
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
 // FP32 variants 4 and 5: the three-product kernel with the Q tile loaded into
-// LDS directly, on 128 and 64 complex columns.  Split variants 4 and 5: both
-// tiles loaded into LDS directly, on four waves with two stages and on eight
-// waves with three (FP64 runs variant 5 as 4).
-constexpr int kNCorr = 6;
+// LDS directly, on 128 and 64 complex columns; variant 6: as 5 with the output
+// tile requested before the reduction.  Split variants 4 and 5: both tiles
+// loaded into LDS directly, on four waves with two stages and on eight waves
+// with three (split runs variant 6 as 5, FP64 runs 5 and 6 as 4).
+constexpr int kNCorr = 7;
 constexpr int kProjKG = 16;
 
 std::atomic<int> g_tune[4] = {{-1}, {-1}, {-1}, {-1}};
+
+// Per-shape tile choices (dcmesh_set_tuning_shape): (kernel, precision, nx, ny,
+// nz, fd_order, n_orb, n_proj) -> variant.  A global choice (g_tune) takes
+// precedence; shapes without an entry use the built-in rules.
+using ShapeKey = std::array<int, 8>;
+std::mutex g_shape_mu;
+std::map<ShapeKey, int> g_shape_tune;
+std::atomic<int> g_shape_count{0};
+
+ShapeKey shape_key(int kernel, int prec, const dcmesh_domain& d) {
+  return {kernel, prec, d.nx, d.ny, d.nz, d.fd_order, d.n_orb, d.n_proj};
+}
+// The tuned variant of this family for this domain: the global choice, else
+// the per-shape entry, else -1.
+int tuned(int kernel, int prec, const dcmesh_domain& d) {
+  const int t = g_tune[kernel].load();
+  if (t >= 0 || g_shape_count.load() == 0) return t;
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  auto it = g_shape_tune.find(shape_key(kernel, prec, d));
+  return it == g_shape_tune.end() ? -1 : it->second;
+}
 
 // The sweep3 variants address a plane of u with 32-bit byte offsets; a domain
 // whose plane spans 2^32 bytes or more uses the default sweep instead.
@@ -115,7 +140,7 @@ int stencil_default_f32(const dcmesh_domain& d) {
   return 1.15 * waste(8, 8) < waste(16, 8) ? 8 : kStencilDefaultF32;
 }
 int stencil_variant(const dcmesh_domain& d, int prec) {
-  const int t = g_tune[DCMESH_KERNEL_STENCIL].load();
+  const int t = tuned(DCMESH_KERNEL_STENCIL, prec, d);
   const int v = t >= 0 ? t : (is_fp64(prec) ? kStencilDefaultF64 : stencil_default_f32(d));
   const long long plane_bytes = (long long)d.nx * d.ny * d.n_orb * (is_fp64(prec) ? 16 : 8);
   return (v >= kFirstSweep3 && plane_bytes >= (1LL << 32)) ? kStencilFallback : v;
@@ -146,6 +171,13 @@ bool direct_split_proj_ok(const dcmesh_domain& d) {
 }
 int proj_variant(const dcmesh_domain& d, int prec) {
   int base = proj_variant_base(d, prec);
+  if (base == 7) {
+    // FP32: the three-product kernel on 64 projectors x 32 complex orbitals
+    // (launch keys 10 and 11: 8-byte and 16-byte loads), for any row length;
+    // other modes run it as 6 (split) or 1 (FP64)
+    if (prec == DCMESH_FP32) return 10 + (wide_proj(d, prec) ? 1 : 0);
+    base = is_split(prec) ? 6 : 1;
+  }
   if (base == 6) {
     if (is_split(prec)) return direct_split_proj_ok(d) ? 6 : 1;
     base = 4;
@@ -171,6 +203,13 @@ bool direct_corr_ok(const dcmesh_domain& d, int prec) {
 }
 int corr_variant(const dcmesh_domain& d, int prec) {
   int base = corr_variant_base(d, prec);
+  if (base == 6) {
+    if (is_split(prec)) return 5;
+    // FP32: the 64-complex-column direct-LDS kernel with the output tile
+    // requested before the reduction (launch keys 11 and 15)
+    if (prec == DCMESH_FP32) return direct_corr_ok(d, prec) ? (wide_corr(d, prec) ? 15 : 11) : 1 + wide_corr(d, prec);
+    base = 4;
+  }
   if (base == 5) {
     if (is_split(prec)) return 5;
     // FP32: the direct-LDS three-product kernel on 64 complex columns
@@ -191,7 +230,7 @@ double proj_waste(const dcmesh_domain& d, int bm, int bn) {
   return (double)(cdiv(d.n_proj, bm) * bm) * (double)(cdiv(2 * d.n_orb, bn) * bn) / (m * n);
 }
 int proj_variant_base(const dcmesh_domain& d, int prec) {
-  const int t = g_tune[DCMESH_KERNEL_PROJECT].load();
+  const int t = tuned(DCMESH_KERNEL_PROJECT, prec, d);
   if (t >= 0) return t;
   if (is_fp64(prec)) return (d.n_proj >= 48 || 2 * d.n_orb >= 48) ? 0 : 1;
   // The cheapest of a few candidates by padded area times the kernel's time
@@ -214,7 +253,7 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   return best;
 }
 int corr_variant_base(const dcmesh_domain& d, int prec) {
-  const int t = g_tune[DCMESH_KERNEL_CORRECT].load();
+  const int t = tuned(DCMESH_KERNEL_CORRECT, prec, d);
   if (t >= 0) return t;
   if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
   // large tiles: both tiles loaded into LDS directly, three stages on eight waves
@@ -408,6 +447,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     const GemmVariant t = is_fp64(prec)  ? kProjF64[v % 4]
                           : is_split(prec) ? kProjSplit[v]
                           : v == kProjDirect + 1 ? GemmVariant{64, 128}
+                          : (v == 10 || v == 11) ? GemmVariant{64, 64}
                                                  : kProjF32[v % 4];
     const DomDesc& D = P.desc[i];
     const size_t b0 = it.size();
@@ -432,7 +472,7 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     const int v = cv(i);
     const GemmVariant t = is_fp64(prec)  ? kCorrF64[v % 4]
                           : is_split(prec) ? kCorrSplit[v]
-                          : (v == 10 || v == 14) ? GemmVariant{64, 128}
+                          : (v == 10 || v == 11 || v == 14 || v == 15) ? GemmVariant{64, 128}
                                                  : kCorrF32[v % 4];
     const DomDesc& D = P.desc[i];
     const size_t b0 = it.size();
@@ -597,11 +637,18 @@ std::map<std::pair<size_t, size_t>, std::shared_ptr<Staging>> g_stage;   // (has
 // repeated calls with changing pointers (chunked runs, the adjoint sweep) reuse
 // a handful of allocations.  Allocation is not allowed under stream capture,
 // so graph creation stages its tables before capturing.
-int get_staging(const Plan& P, bool capturing, std::shared_ptr<Staging>* out) {
-  const size_t bytes = P.bytes_tables;
-  std::vector<char> img(bytes, 0);
+// The head of the workspace as the kernels read it: domain descriptors, then
+// the work lists.
+std::vector<char> table_image(const Plan& P) {
+  std::vector<char> img(P.bytes_tables, 0);
   std::memcpy(img.data(), P.desc.data(), sizeof(DomDesc) * P.n_dom);
   std::memcpy(img.data() + P.off_items, P.items.data(), sizeof(Item) * P.items.size());
+  return img;
+}
+
+int get_staging(const Plan& P, bool capturing, std::shared_ptr<Staging>* out) {
+  const size_t bytes = P.bytes_tables;
+  const std::vector<char> img = table_image(P);
   const size_t hsh = std::hash<std::string>()(std::string(img.data(), img.size()));
   std::shared_ptr<Staging> st;
   std::lock_guard<std::mutex> lk(g_stage_mu);
@@ -795,6 +842,8 @@ void launch_project(const Ctx& c, int u_slot, int a_slot = -1) {
         case 6: k_project<T, T, 64, 128, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 7: k_project<T, T, 128, 256, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 9: k_project3m_dl<64, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 10: k_project3m<64, 32, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        case 11: k_project3m<64, 32, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         default: k_project3m_dl<128, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
       }
     } else {
@@ -834,7 +883,9 @@ void launch_correct(const Ctx& c, int out_slot) {
         case 7: k_correct<T, T, 128, 256, 32, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 8: k_correct3m_dl<64, 128, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 10: k_correct3m_dl<64, 64, 16, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 11: k_correct3m_dl<64, 64, 16, 2, true><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 14: k_correct3m_dl<64, 64, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        case 15: k_correct3m_dl<64, 64, 16, 4, true><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         default: k_correct3m_dl<64, 128, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       }
     } else {
@@ -1046,8 +1097,9 @@ struct CallSetup {
 int prepare(CallSetup& cs, const dcmesh_domain* doms, int32_t n_dom, int32_t prec, void* work,
             size_t work_bytes, hipStream_t s, uint32_t flags, const std::function<void(Plan&)>& fill) {
   Plan& P = cs.P;
+  int rc;
   build_plan(P, doms, n_dom, prec, (char*)work);
-  int rc = validate_work(work, work_bytes, P.bytes_total);
+  rc = validate_work(work, work_bytes, P.bytes_total);
   if (rc) return rc;
   rc = check_device();
   if (rc) return rc;
@@ -1593,6 +1645,32 @@ int dcmesh_set_tuning(int32_t kernel, int32_t variant) {
   if (rc) return rc;
   if (variant < -1 || variant >= count) return fail(DCMESH_ERR_INVALID_ARGUMENT, "variant out of range");
   g_tune[kernel].store(variant);
+  return DCMESH_OK;
+}
+
+int dcmesh_set_tuning_shape(int32_t kernel, int32_t precision, const dcmesh_domain* shape, int32_t variant) {
+  if (!shape) return fail(DCMESH_ERR_INVALID_ARGUMENT, "shape is NULL");
+  if (precision < DCMESH_FP64 || precision > DCMESH_SPLIT_FP16)
+    return fail(DCMESH_ERR_INVALID_ARGUMENT, "unknown precision " + std::to_string(precision));
+  if (kernel == DCMESH_KERNEL_ZSEG) return fail(DCMESH_ERR_INVALID_ARGUMENT, "the z segment is not set per shape");
+  int count = 0;
+  int rc = dcmesh_tuning_options(kernel, &count);
+  if (rc) return rc;
+  if (variant < -1 || variant >= count) return fail(DCMESH_ERR_INVALID_ARGUMENT, "variant out of range");
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  const ShapeKey k = shape_key(kernel, precision, *shape);
+  if (variant < 0)
+    g_shape_tune.erase(k);
+  else
+    g_shape_tune[k] = variant;
+  g_shape_count.store((int)g_shape_tune.size());
+  return DCMESH_OK;
+}
+
+int dcmesh_clear_tuning_shapes(void) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_shape_tune.clear();
+  g_shape_count.store(0);
   return DCMESH_OK;
 }
 

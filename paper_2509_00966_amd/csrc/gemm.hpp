@@ -838,7 +838,7 @@ __global__ __launch_bounds__(kBlock) void k_correct3m(const DomDesc* __restrict_
 // k_correct3m.  Odd Q rows are stored rotated by 16 floats, so the two 16-lane
 // quarters of a half-wave, which read consecutive rows, use disjoint LDS banks.  Each plane's buffer ends after n_proj rows, so rows past it read
 // as zero; columns past n_orb reach only outputs that are not stored.
-template <int BMG, int BNC, int KC, int VW>
+template <int BMG, int BNC, int KC, int VW, bool PF = false>
 __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restrict__ doms,
                                                          const Item* __restrict__ items, int out_slot) {
   constexpr int TM = BMG / 32, TN = BNC / 32;
@@ -883,6 +883,26 @@ __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restri
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) k1[i][j] = k2[i][j] = k3[i][j] = f32x4{0, 0, 0, 0};
+  // PF: the output tile this lane adds into is requested before the
+  // reduction, so that its latency is spent under the products (a short
+  // reduction, as in small domains, otherwise ends on a full memory round
+  // trip); it costs about 40 registers, one wave per SIMD
+  float2 prev[TM][TN][4];
+  auto load_prev = [&](int i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
+        const int n = n0 + wn0 + j * 16 + ll;
+        prev[i][j][r] = (g < D.n_grid && n < no) ? *reinterpret_cast<const float2*>(out + (g * no + n) * 2)
+                                                  : make_float2(0.f, 0.f);
+      }
+  };
+  if constexpr (PF) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i) load_prev(i);
+  }
 
   Vec<float, VW> ra[RA];
   auto load_a = [&](int st) {
@@ -979,16 +999,7 @@ __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restri
   // out += result, one 16-row tile at a time (reads before writes)
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
-    float2 prev[TN][4];
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const long long g = g0 + wm0 + i * 16 + 4 * lk + r;
-        const int n = n0 + wn0 + j * 16 + ll;
-        prev[j][r] = (g < D.n_grid && n < no) ? *reinterpret_cast<const float2*>(out + (g * no + n) * 2)
-                                               : make_float2(0.f, 0.f);
-      }
+    if constexpr (!PF) load_prev(i);
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -997,7 +1008,8 @@ __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restri
         const int n = n0 + wn0 + j * 16 + ll;
         if (g < D.n_grid && n < no)
           *reinterpret_cast<float2*>(out + (g * no + n) * 2) =
-              make_float2(prev[j][r].x + (k1[i][j][r] - k3[i][j][r]), prev[j][r].y + (k1[i][j][r] + k2[i][j][r]));
+              make_float2(prev[i][j][r].x + (k1[i][j][r] - k3[i][j][r]),
+                          prev[i][j][r].y + (k1[i][j][r] + k2[i][j][r]));
       }
   }
 }

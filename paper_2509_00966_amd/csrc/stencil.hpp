@@ -91,6 +91,18 @@ __device__ __forceinline__ void halo_xy(int hidx, int& lx, int& ly) {
   }
 }
 
+// Barrier of the LDS plane exchange in the z sweeps: waits for this wave's
+// own LDS reads and writes (lgkmcnt(0)), then for the other waves.  Global
+// loads stay in flight across it: a __syncthreads() fence would also wait for
+// every prefetch of later planes, draining the memory pipeline once per plane.
+// The registers those loads fill are waited for where they are used.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Items: (dom, x tile, y tile, (z segment << 16) | orbital chunk).
 // D.zseg planes per segment.  Energy partials: one per item, at
 // e_loc[blockIdx.x - D.item0_stencil].  Density partials at
@@ -540,7 +552,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep3(const DomDesc* __restrict
 #pragma unroll
     for (int j = 0; j < R; ++j) hq[k][j] = at(ub, wrap(z_begin + 1 + j, nz), ho[k]);
   }
-  __syncthreads();
+  lds_barrier();
 
   double e_acc = 0.0;
   for (int z = z_begin; z < z_end; ++z) {
@@ -618,7 +630,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep3(const DomDesc* __restrict
 #pragma unroll
       for (int j = 0; j < R; ++j) hq[k][j] = hq[k][j + 1];
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (args.want_energy) {
     const double s = block_sum<double, NT / kWave>(e_acc, red);
@@ -640,7 +652,7 @@ __device__ __forceinline__ void with_phases(F&& f, std::integer_sequence<int, Ps
   f(std::integral_constant<int, Ps>{}...);
 }
 
-template <typename T, int R, int OC, int TX, int TY, int NT, int GM>
+template <typename T, int R, int OC, int TX, int TY, int NT, int GM, bool HB>
 __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, const StencilArgs& args,
                                             const StencilW<T>& w, Cplx<T>* lds, double* red) {
   using C = Cplx<T>;
@@ -654,10 +666,10 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
   const int zseg = it.c >> 16, oc0 = chunk * OC;
   const int z_begin = zseg * D.zseg, z_end = min(z_begin + D.zseg, nz);
 
+  // HB: a base other than u is read (otherwise the base is u, or none)
   const bool base_is_u = args.base_slot == args.u_slot;
   const char* __restrict__ ub = (const char*)D.slot[args.u_slot];
-  const char* __restrict__ bb =
-      (args.base_slot < SLOT_NONE && !base_is_u) ? (const char*)D.slot[args.base_slot] : nullptr;
+  const char* __restrict__ bb = HB ? (const char*)D.slot[args.base_slot] : nullptr;
   char* __restrict__ ob = (char*)D.slot[args.out_slot];
   const char* __restrict__ vb = (const char*)D.v;
   const T* __restrict__ occ = (const T*)D.occ;
@@ -687,6 +699,9 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
     co[k] = (gc * (unsigned)no + (unsigned)nl) * (unsigned)sizeof(C);
     cv[k] = gc * (unsigned)sizeof(T);
   }
+  // halo cells: slots past the strips write a scratch cell past both planes,
+  // so every LDS store and every load is unconditional (straight-line code
+  // lets the compiler wait for each prefetch by count)
   int hl[KH];
   unsigned ho[KH];
 #pragma unroll
@@ -694,7 +709,7 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
     const int hidx = tc + k * Cfg::kThrCols;
     int lx = R, ly = R;
     if (hidx < Cfg::kH) halo_xy<R, TX, TY>(hidx, lx, ly);
-    hl[k] = hidx < Cfg::kH ? (ly * Cfg::kLX + lx) * OC + o : -1;
+    hl[k] = hidx < Cfg::kH ? (ly * Cfg::kLX + lx) * OC + o : 2 * PLANE + o;
     const unsigned gc = (unsigned)(wrap(y0 + ly - R, ny) * nx + wrap(x0 + lx - R, nx));
     ho[k] = (gc * (unsigned)no + (unsigned)nl) * (unsigned)sizeof(C);
   }
@@ -712,30 +727,32 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
   for (int k = 0; k < KP; ++k) {
 #pragma unroll
     for (int s = 0; s < 2 * R + 1; ++s) q[k][s] = at(ub, wrap(z_begin - R + s, nz), co[k]);
-    bq[k][0] = bb ? at(bb, z_begin, co[k]) : C{0, 0};
+    if constexpr (HB) bq[k][0] = at(bb, z_begin, co[k]);
     vq[k][0] = vat(z_begin, cv[k]);
     lds[lc[k]] = q[k][R];
   }
 #pragma unroll
   for (int k = 0; k < KH; ++k) {
-    if (hl[k] >= 0) lds[hl[k]] = at(ub, z_begin, ho[k]);
+    lds[hl[k]] = at(ub, z_begin, ho[k]);
 #pragma unroll
     for (int j = 1; j <= R; ++j) hq[k][j] = at(ub, wrap(z_begin + j, nz), ho[k]);
   }
-  __syncthreads();
+  lds_barrier();
 
   double e_acc = 0.0;
   // one plane at phase P = (z - z_begin) % U; false once the segment is done
   auto plane_step = [&](auto PC, int z) -> bool {
     constexpr int P = decltype(PC)::value;
     const bool more = z + 1 < z_end;
-    if (more) {
-      const int zq = wrap(z + 1 + R, nz);
+    {
+      // the next plane's loads, issued on the segment's last plane too (a
+      // plane that exists: z + 1 clamped to the segment), unused then
+      const int zq = wrap(z + 1 + R, nz), zn = more ? z + 1 : z;
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         q[k][(P + 2 * R + 1) % U] = at(ub, zq, co[k]);
-        bq[k][(P + 1) % 2] = bb ? at(bb, z + 1, co[k]) : C{0, 0};
-        vq[k][(P + 1) % 2] = vat(z + 1, cv[k]);
+        if constexpr (HB) bq[k][(P + 1) % 2] = at(bb, zn, co[k]);
+        vq[k][(P + 1) % 2] = vat(zn, cv[k]);
       }
 #pragma unroll
       for (int k = 0; k < KH; ++k) hq[k][P % H] = at(ub, zq, ho[k]);
@@ -781,7 +798,8 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
       if (ok[k]) {
         if (args.want_energy) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
         if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
-        const C b = base_is_u ? c0 : bq[k][P % 2];
+        C b = base_is_u ? c0 : C{0, 0};
+        if constexpr (HB) b = bq[k][P % 2];
         *(C*)(ob + (long long)z * pbytes + co[k]) =
             C{cre * acc.re - cim * acc.im + b.re, cre * acc.im + cim * acc.re + b.im};
       }
@@ -793,9 +811,8 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
 #pragma unroll
     for (int k = 0; k < KP; ++k) Ln[lc[k]] = q[k][(P + R + 1) % U];
 #pragma unroll
-    for (int k = 0; k < KH; ++k)
-      if (hl[k] >= 0) Ln[hl[k]] = hq[k][(P + 1) % H];
-    __syncthreads();
+    for (int k = 0; k < KH; ++k) Ln[hl[k]] = hq[k][(P + 1) % H];
+    lds_barrier();
     return true;
   };
   auto run = [&](auto... PCs) {
@@ -814,17 +831,27 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict
                                                        const Item* __restrict__ items,
                                                        StencilArgs args) {
   using Cfg = SweepCfg<R, OC, TX, TY, NT>;
-  __shared__ Cplx<T> lds[2 * Cfg::kLY * Cfg::kLX * OC];
+  // two centre planes, then one scratch cell per orbital lane for the halo
+  // slots past the strips
+  __shared__ Cplx<T> lds[2 * Cfg::kLY * Cfg::kLX * OC + OC];
   __shared__ double red[NT / kWave];
   const Item it = items[blockIdx.x];
   const DomDesc& D = doms[it.dom];
   const StencilW<T> w = stencil_weights<T>(D, args.step);
-  if (args.want_density || w.A[0] != (T)0 || w.A[1] != (T)0)
-    sweep4_body<T, R, OC, TX, TY, NT, 7>(D, it, args, w, lds, red);
-  else if (w.A[2] != (T)0)
-    sweep4_body<T, R, OC, TX, TY, NT, 4>(D, it, args, w, lds, red);
+  const bool hb = args.base_slot < SLOT_NONE && args.base_slot != args.u_slot;
+  auto body = [&](auto hbc) {
+    constexpr bool HB = decltype(hbc)::value;
+    if (args.want_density || w.A[0] != (T)0 || w.A[1] != (T)0)
+      sweep4_body<T, R, OC, TX, TY, NT, 7, HB>(D, it, args, w, lds, red);
+    else if (w.A[2] != (T)0)
+      sweep4_body<T, R, OC, TX, TY, NT, 4, HB>(D, it, args, w, lds, red);
+    else
+      sweep4_body<T, R, OC, TX, TY, NT, 0, HB>(D, it, args, w, lds, red);
+  };
+  if (hb)
+    body(std::true_type{});
   else
-    sweep4_body<T, R, OC, TX, TY, NT, 0>(D, it, args, w, lds, red);
+    body(std::false_type{});
 }
 
 // rho[g] = sum_chunks dpart[c][g][0];  j[g][d] = sum_chunks dpart[c][g][1 + d] + A_d rho.

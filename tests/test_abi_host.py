@@ -148,3 +148,16 @@ def test_workspace_size_does_not_depend_on_tuning(precision):
     finally:
         for k in range(4):
             L.lib.dcmesh_set_tuning(k, -1)
+
+
+def test_tuning_shape_table_validation():
+    L = _lib()
+    d = _dom(L)
+    assert L.lib.dcmesh_set_tuning_shape(1, 1, None, 0) == 1
+    assert L.lib.dcmesh_set_tuning_shape(1, 9, d, 0) == 1          # precision
+    assert L.lib.dcmesh_set_tuning_shape(3, 1, d, 1) == 1          # the z segment is global only
+    assert L.lib.dcmesh_set_tuning_shape(1, 1, d, 99) == 1         # variant out of range
+    assert L.lib.dcmesh_set_tuning_shape(7, 1, d, 0) == 1          # unknown family
+    assert L.lib.dcmesh_set_tuning_shape(1, 1, d, 2) == 0
+    assert L.lib.dcmesh_set_tuning_shape(1, 1, d, -1) == 0         # removes the entry
+    assert L.lib.dcmesh_clear_tuning_shapes() == 0

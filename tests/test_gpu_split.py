@@ -3,8 +3,8 @@
 Operator level: the library's H psi in split mode against the oracle's
 split-form operator (same two-term rounding of every operand, products summed
 exactly) -- the remaining difference is FP32 accumulation, bounded here by
-2 U32 kappa per error view (kappa: the condition number of the operator's sum
-of terms, helpers.fp32_operator_tol).  Propagation level: the split path against the FP64 oracle
+2 U32 kappa in the norm views and 4 U32 kappa element-wise (kappa: the
+condition number of the operator's sum of terms, helpers.fp32_operator_tol).  Propagation level: the split path against the FP64 oracle
 after 20 steps, within 1e-4 (BF16) / 1e-5 (FP16) relative on psi.
 """
 import numpy as np

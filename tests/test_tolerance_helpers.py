@@ -39,7 +39,10 @@ def test_tolerance_is_scale_free():
     dom = make_domain(13, (9, 9, 9), 4, 1, proj_per_atom=8, h=0.4, fd_order=4)
     A = np.array([0.0, 0.0, 0.2])
     hu = H.apply_h(dom, A, dom.psi)
-    t1 = fp32_operator_tol(dom, A, dom.psi, hu)
-    t2 = fp32_operator_tol(dom, A, 3.0 * dom.psi, 3.0 * hu)
+    t1 = fp32_operator_tol(dom, A, dom.psi, hu, occ_scale=False)
+    t2 = fp32_operator_tol(dom, A, 3.0 * dom.psi, 3.0 * hu, occ_scale=False)
+    # the occupation factors scale the magnitudes and the reference alike
+    t3 = fp32_operator_tol(dom, A, dom.psi, hu * dom.occ[None, :], occ_scale=True)
     assert np.allclose(t1, t2, rtol=1e-12)
+    assert np.allclose(t1, t3, rtol=1e-12)
     assert all(x > 0 for x in t1)
