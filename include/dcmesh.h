@@ -43,7 +43,8 @@
  * No entry point synchronises or reads device memory on the host unless
  * DCMESH_FLAG_CHECK_FINITE is set.  A call made under stream capture must find
  * its tables staged (the allocation above is not allowed there):
- * dcmesh_graph_create stages them before it captures.
+ * dcmesh_graph_create stages them before it captures, and dcmesh_step_noalloc
+ * needs no staging.
  *
  * Errors: each entry point returns a DCMESH_* status; 0 means success.  All
  * arguments are validated on the host before any HIP call, so an invalid
@@ -155,6 +156,24 @@ int dcmesh_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
                 const double* a_dev, int32_t a_per_domain, int64_t a_stride,
                 double dt, int32_t n_steps, const dcmesh_obs* obs,
                 void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* dcmesh_step without a workspace argument, for callers that cannot allocate
+ * device memory: work recorded under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The workspace is a static device array of
+ * 64 MiB (2^26 bytes) that every GPU the library runs on holds until the
+ * process ends; domains that need more (dcmesh_workspace_bytes) make the call
+ * fail with DCMESH_ERR_WORKSPACE before any HIP call.  The call allocates
+ * nothing: no device memory, no pinned staging buffer (the work lists reach the
+ * array through kernel arguments), no events (DCMESH_FLAG_PROFILE is
+ * rejected).  The array keeps the last call's contents; every call writes
+ * whatever it later reads, so nothing needs clearing between calls.  All calls
+ * on one GPU share its array: calls that overlap on one GPU (two streams, two
+ * threads) race, and the caller must serialise them.  Other arguments,
+ * results and errors as dcmesh_step (bitwise the same results). */
+int dcmesh_step_noalloc(const dcmesh_domain* doms, int32_t n_dom, int32_t precision,
+                        const double* a_dev, int32_t a_per_domain, int64_t a_stride,
+                        double dt, int32_t n_steps, const dcmesh_obs* obs,
+                        uint32_t flags, void* stream);
 
 /* Eq. 2 with the nonlocal operator of Eq. 5: every step applies
  *     N T4(-i dt h_loc(A_k)) N,   N psi = (psi - delta Psi0 h^3 Psi0^H psi) / |.|,

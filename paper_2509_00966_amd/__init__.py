@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     set_tuning,
     step,
     step_eq2,
+    step_noalloc,
     set_tuning_shape,
     clear_tuning_shapes,
     step_maxwell,

@@ -25,7 +25,7 @@ FAMILIES = ("stencil", "project", "reduce", "correct", "density", "energy", "adj
 KERNEL = {"stencil": 0, "project": 1, "correct": 2, "zseg": 3}
 
 EXPORTS = (
-    "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_step_eq2", "dcmesh_density", "dcmesh_occupations",
+    "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_step_noalloc", "dcmesh_step_eq2", "dcmesh_density", "dcmesh_occupations",
     "dcmesh_current", "dcmesh_step_maxwell", "dcmesh_adjoint_step",
     "dcmesh_graph_create", "dcmesh_graph_launch", "dcmesh_graph_destroy",
     "dcmesh_set_tuning", "dcmesh_tuning_options", "dcmesh_set_tuning_shape", "dcmesh_clear_tuning_shapes", "dcmesh_profile_collect", "dcmesh_last_error",
@@ -67,6 +67,7 @@ def _load():
     sig = {
         "dcmesh_workspace_bytes": [dom_p, I32, I32, U32, ctypes.POINTER(SZ)],
         "dcmesh_step": [dom_p, I32, I32, P, I32, I64, D, I32, ctypes.POINTER(DcmeshObs), P, SZ, U32, P],
+        "dcmesh_step_noalloc": [dom_p, I32, I32, P, I32, I64, D, I32, ctypes.POINTER(DcmeshObs), U32, P],
         "dcmesh_density": [dom_p, I32, I32, P, I32, ctypes.POINTER(DcmeshDensityOut), P, SZ, U32, P],
         "dcmesh_step_eq2": [dom_p, I32, I32, ctypes.POINTER(P), D, P, I32, I64, D, I32, P, SZ, U32, P],
         "dcmesh_occupations": [dom_p, I32, I32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P,

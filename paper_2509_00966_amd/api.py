@@ -140,6 +140,23 @@ def step(domains: Sequence[Domain], a: torch.Tensor, dt: float, n_steps: int, pr
                           float(dt), int(n_steps), o, work.ptr, work.nbytes, flags, _stream(stream)))
 
 
+def step_noalloc(domains: Sequence[Domain], a: torch.Tensor, dt: float, n_steps: int, precision: str,
+                 obs: Optional[List[dict]] = None, a_per_domain: bool = False, check_finite: bool = False,
+                 stream=None):
+    """``step`` without a workspace: the library's static device scratch
+    (dcmesh_step_noalloc; 64 MiB, so small domains only)."""
+    arr = _doms(domains, precision)
+    if a.dtype != torch.float64 or not a.is_contiguous() or not a.is_cuda:
+        raise ValueError("a must be a contiguous float64 GPU tensor")
+    o = None
+    if obs is not None:
+        o = (DcmeshObs * len(domains))(*[DcmeshObs(_ptr(x.get("rho")), _ptr(x.get("j")), _ptr(x.get("energy")))
+                                         for x in obs])
+    flags = _lib.FLAG_CHECK_FINITE if check_finite else 0
+    check(lib.dcmesh_step_noalloc(arr, len(domains), PRECISION[precision], a.data_ptr(), int(a_per_domain),
+                                  a.shape[-2], float(dt), int(n_steps), o, flags, _stream(stream)))
+
+
 def step_eq2(domains: Sequence[Domain], psi0: Sequence[torch.Tensor], v_nl: float, a: torch.Tensor, dt: float,
              n_steps: int, precision: str, work: Workspace, a_per_domain: bool = False, profile: bool = False,
              stream=None):

@@ -29,6 +29,11 @@
 
 using namespace dcm;
 
+// Device scratch of the allocation-free entry point dcmesh_step_noalloc (its
+// maximum workspace size; see dcmesh.h).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -701,6 +706,56 @@ int stage_tables(const Plan& P, char* work, hipStream_t s, bool capturing, std::
   return DCMESH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of dcmesh_step_noalloc
+// ---------------------------------------------------------------------------
+// Callers that cannot allocate device memory (work under graph capture, tight
+// serving loops) get the workspace from this array instead; each GPU the
+// library runs on holds its own copy until the process ends.  Its device
+// address comes from hipGetSymbolAddress, once per device: in host code the
+// array's name is not a device address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Tables reach the scratch through kernel arguments (no pinned staging buffer
+// is allocated): one launch per chunk, in stream order before the work.
+constexpr int kUploadChunk = 1024;
+struct UploadChunk { unsigned char b[kUploadChunk]; };
+__global__ void k_upload(unsigned char* dst, UploadChunk c, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = c.b[i];
+}
+
+// Device address of this device's copy of the scratch array.  Looked up
+// once per device with that device current (the caller's current device).
+int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DCMESH_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DCMESH_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DCMESH_OK;
+}
+
+int upload_tables(const Plan& P, char* dst, hipStream_t s) {
+  const std::vector<char> img = table_image(P);
+  UploadChunk c;
+  for (size_t off = 0; off < img.size(); off += kUploadChunk) {
+    const int n = (int)std::min<size_t>(kUploadChunk, img.size() - off);
+    std::memcpy(c.b, img.data() + off, n);
+    k_upload<<<1, kBlock, 0, s>>>((unsigned char*)dst + off, c, n);
+  }
+  HIPCHK(hipGetLastError());
+  return DCMESH_OK;
+}
+
 int check_device() {
   static std::once_flag once;
   static int status = DCMESH_OK;
@@ -1094,10 +1149,28 @@ struct CallSetup {
   std::shared_ptr<Staging> keep;
 };
 
+// use_static: the workspace is the static scratch (dcmesh_step_noalloc; work
+// and work_bytes are ignored), with the tables uploaded through kernel
+// arguments instead of a pinned staging copy.
 int prepare(CallSetup& cs, const dcmesh_domain* doms, int32_t n_dom, int32_t prec, void* work,
-            size_t work_bytes, hipStream_t s, uint32_t flags, const std::function<void(Plan&)>& fill) {
+            size_t work_bytes, hipStream_t s, uint32_t flags, const std::function<void(Plan&)>& fill,
+            bool use_static = false) {
   Plan& P = cs.P;
   int rc;
+  if (use_static) {
+    if (flags & DCMESH_FLAG_PROFILE)
+      return fail(DCMESH_ERR_INVALID_ARGUMENT, "PROFILE creates events: not available without allocation");
+    build_plan(P, doms, n_dom, prec, nullptr);
+    if (P.bytes_total > kScratchBytes)
+      return fail(DCMESH_ERR_WORKSPACE, "these domains need " + std::to_string(P.bytes_total) +
+                                            " bytes of workspace; the static scratch holds " +
+                                            std::to_string(kScratchBytes));
+    rc = check_device();
+    if (rc) return rc;
+    rc = scratch_address(&work);
+    if (rc) return rc;
+    work_bytes = kScratchBytes;
+  }
   build_plan(P, doms, n_dom, prec, (char*)work);
   rc = validate_work(work, work_bytes, P.bytes_total);
   if (rc) return rc;
@@ -1109,7 +1182,8 @@ int prepare(CallSetup& cs, const dcmesh_domain* doms, int32_t n_dom, int32_t pre
   if ((flags & DCMESH_FLAG_PROFILE) && cap != hipStreamCaptureStatusNone)
     return fail(DCMESH_ERR_INVALID_ARGUMENT, "PROFILE cannot be used under stream capture");
   t_prof_on = (flags & DCMESH_FLAG_PROFILE) != 0;
-  rc = stage_tables(P, (char*)work, s, cap != hipStreamCaptureStatusNone, &cs.keep);
+  rc = use_static ? upload_tables(P, (char*)work, s)
+                  : stage_tables(P, (char*)work, s, cap != hipStreamCaptureStatusNone, &cs.keep);
   if (rc) return rc;
   cs.c = Ctx{&P, (const DomDesc*)work, (const Item*)((char*)work + P.off_items), s};
   return DCMESH_OK;
@@ -1209,7 +1283,8 @@ int finish(CallSetup& cs, uint32_t flags) {
 
 int step_impl(const dcmesh_domain* doms, int32_t n_dom, int32_t prec, const double* a_dev,
               int32_t a_per_domain, int64_t a_stride, double dt, int32_t n_steps, const dcmesh_obs* obs,
-              void* work, size_t work_bytes, uint32_t flags, hipStream_t s, CallSetup& cs) {
+              void* work, size_t work_bytes, uint32_t flags, hipStream_t s, CallSetup& cs,
+              bool use_static = false) {
   int rc = validate_domains(doms, n_dom, prec);
   if (rc) return rc;
   if (n_steps < 0) return fail(DCMESH_ERR_INVALID_ARGUMENT, "n_steps must be >= 0");
@@ -1237,7 +1312,7 @@ int step_impl(const dcmesh_domain* doms, int32_t n_dom, int32_t prec, const doub
         D.energy = as_global(obs[i].energy);
       }
     }
-  });
+  }, use_static);
   if (rc) return rc;
   if (is_fp64(prec))
     rc = run_step<double>(cs, n_steps, dt, want_rho_j, want_e);
@@ -1289,6 +1364,14 @@ int dcmesh_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, con
   CallSetup cs;
   return step_impl(doms, n_dom, precision, a_dev, a_per_domain, a_stride, dt, n_steps, obs, work, work_bytes,
                    flags, (hipStream_t)stream, cs);
+}
+
+int dcmesh_step_noalloc(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const double* a_dev,
+                        int32_t a_per_domain, int64_t a_stride, double dt, int32_t n_steps,
+                        const dcmesh_obs* obs, uint32_t flags, void* stream) {
+  CallSetup cs;
+  return step_impl(doms, n_dom, precision, a_dev, a_per_domain, a_stride, dt, n_steps, obs, nullptr, 0, flags,
+                   (hipStream_t)stream, cs, true);
 }
 
 int dcmesh_step_eq2(const dcmesh_domain* doms, int32_t n_dom, int32_t precision, const void* const* psi0,

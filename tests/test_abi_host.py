@@ -161,3 +161,13 @@ def test_tuning_shape_table_validation():
     assert L.lib.dcmesh_set_tuning_shape(1, 1, d, 2) == 0
     assert L.lib.dcmesh_set_tuning_shape(1, 1, d, -1) == 0         # removes the entry
     assert L.lib.dcmesh_clear_tuning_shapes() == 0
+
+
+def test_noalloc_rejects_before_any_hip_call():
+    L = _lib()
+    # a 64^3 domain with 128 orbitals needs far more than the 64 MiB scratch
+    big = _dom(L, nx=64, ny=64, nz=64, n_orb=128, n_proj=512)
+    rc = L.lib.dcmesh_step_noalloc(big, 1, 1, 0x10000, 0, 1, 0.02, 1, None, 0, None)
+    assert rc == 3, L.lib.dcmesh_last_error()
+    assert b"static scratch" in L.lib.dcmesh_last_error()
+    assert L.lib.dcmesh_step_noalloc(_dom(L, n_orb=0), 1, 1, 0x10000, 0, 1, 0.02, 1, None, 0, None) == 1
