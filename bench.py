@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=100,
                     help="batched: steps per captured graph when K is a multiple of it (else one K-step graph)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--tuning", default="",
+                    help="global tile choices before the run, e.g. stencil=9,project=8,correct=7")
     ap.add_argument("--stream-ceiling", action="store_true",
                     help="only measure what plain streams reach on this GPU (1 GiB operands: a read-only "
                          "sum, a copy, and a two-read one-write add) and print one JSON line")
@@ -104,6 +106,10 @@ def main():
     import paper_2509_00966_amd as api
     from synth import config, pulse_midpoints
 
+    for kv in filter(None, args.tuning.split(",")):
+        fam, v = kv.split("=")
+        api.set_tuning(fam.strip(), int(v))
+        log(f"bench: tuning {fam.strip()} = {int(v)}")
     if args.workload == "batched":
         return run_batched(args)
     if args.workload == "adjoint":

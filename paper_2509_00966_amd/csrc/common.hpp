@@ -176,6 +176,18 @@ __device__ __forceinline__ const DCM_GLOBAL char* proj_operand(const DomDesc& D,
   return (const DCM_GLOBAL char*)D.proj_r + (long long)(-2 - a_slot) * D.n_grid * D.n_proj * 2 * ES;
 }
 
+// Barrier for an LDS exchange: waits for this wave's own LDS reads and
+// writes (lgkmcnt(0)), then for the other waves.  Global loads stay in flight
+// across it: a __syncthreads() fence would also wait for every prefetch in
+// flight, draining the memory pipeline at each stage.  The registers those
+// loads fill are waited for where they are used.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Sum over a block of NW waves (lds holds NW values); result valid in
 // thread 0, added in wave order.
 template <typename T, int NW = kBlock / kWave>

@@ -89,12 +89,13 @@ const GemmVariant kProjF32[] = {{128, 128}, {64, 64}, {64, 128}, {128, 256}};
 const GemmVariant kProjF64[] = {{64, 64}, {32, 32}, {64, 32}, {32, 64}};
 // FP32 variants 4 and 5: the three-product kernel with direct LDS loads on
 // 128 and 64 projectors; variant 7: the three-product kernel through
-// registers on 64 projectors x 32 complex orbitals (any row length).  Split
+// registers on 64 projectors x 32 complex orbitals (any row length); variant
+// 8: every orbital of a domain (up to 96) in one block, 64 projectors.  Split
 // variants 4, 5 and 6: the projector planes loaded into LDS directly, on four
 // waves with two stages (128 x 128), on eight waves with three (128 x 256),
 // and on four waves with two stages (64 x 64).  Other modes run variants 5
 // and 6 as 4 (FP64) or 5 and 4 (FP32), and 7 as 1 (FP64) or 6 (split).
-constexpr int kNProj = 8;
+constexpr int kNProj = 9;
 constexpr int kProjDirect = 8; // its launch key
 const GemmVariant kCorrF32[] = {{64, 256}, {64, 128}, {64, 64}, {128, 256}};
 // split-precision kernels (variant 2 of each stages twice as much per LDS pass)
@@ -103,10 +104,11 @@ const GemmVariant kCorrSplit[] = {{64, 256}, {64, 128}, {64, 256}, {128, 256}, {
 const GemmVariant kCorrF64[] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
 // FP32 variants 4 and 5: the three-product kernel with the Q tile loaded into
 // LDS directly, on 128 and 64 complex columns; variant 6: as 5 with the output
-// tile requested before the reduction.  Split variants 4 and 5: both tiles
+// tile requested before the reduction; variant 7: every orbital of a domain
+// (up to 96) in one block of 64 grid rows.  Split variants 4 and 5: both tiles
 // loaded into LDS directly, on four waves with two stages and on eight waves
 // with three (split runs variant 6 as 5, FP64 runs 5 and 6 as 4).
-constexpr int kNCorr = 7;
+constexpr int kNCorr = 8;
 constexpr int kProjKG = 16;
 
 std::atomic<int> g_tune[4] = {{-1}, {-1}, {-1}, {-1}};
@@ -134,15 +136,15 @@ int tuned(int kernel, int prec, const dcmesh_domain& d) {
 
 // The sweep3 variants address a plane of u with 32-bit byte offsets; a domain
 // whose plane spans 2^32 bytes or more uses the default sweep instead.
-// FP32 default: the 16 x 8 column tile, or the 8 x 8 sweep (variant 8) where
-// the wider tile pads the x edge enough to outweigh the narrower tile's
-// larger halo share (time per useful point 1.15x, measured on batches of
-// equal small domains).
+// FP32 default: the 16 x 8 column tile, or the 8 x 8 sweep of the same kind
+// (variant 9) where the wider tile pads the x edge enough to outweigh the
+// narrower tile's larger halo share (time per useful point 1.15x, measured on
+// batches of equal small domains).
 int stencil_default_f32(const dcmesh_domain& d) {
   auto waste = [&](int tx, int ty) {
     return (double)(cdiv(d.nx, tx) * tx) * (double)(cdiv(d.ny, ty) * ty) / ((double)d.nx * d.ny);
   };
-  return 1.15 * waste(8, 8) < waste(16, 8) ? 8 : kStencilDefaultF32;
+  return 1.15 * waste(8, 8) < waste(16, 8) ? 9 : kStencilDefaultF32;
 }
 int stencil_variant(const dcmesh_domain& d, int prec) {
   const int t = tuned(DCMESH_KERNEL_STENCIL, prec, d);
@@ -174,8 +176,34 @@ bool direct_split_proj_ok(const dcmesh_domain& d) {
   const long long ldbt = (2LL * d.nx * d.ny * d.nz + 7) / 8 * 8;
   return 128 * 2 * ldbt + 4 * ldbt < (1LL << 31);
 }
+// The narrow FP32 products cover all orbitals of a domain in one block of
+// 16 NB orbitals, NB <= kNarrowMax.
+constexpr int kNarrowMax = 6;
+bool narrow_ok(const dcmesh_domain& d, int prec) { return prec == DCMESH_FP32 && d.n_orb <= 16 * kNarrowMax; }
+int narrow_nb(const dcmesh_domain& d) { return (d.n_orb + 15) / 16; }
+constexpr int kProjNarrow = 12, kCorrNarrow = 16;   // first launch keys (+ 2 (NB - 1) + wide)
+constexpr int kSplitNarrow = 8;                     // split modes: first launch key (+ NB - 1)
+bool narrow_split_ok(const dcmesh_domain& d, int prec) { return is_split(prec) && d.n_orb <= 16 * kNarrowMax; }
+// The narrow kernels are the default where they pad the orbitals less than a
+// 64-orbital tile does (n_orb mod 64 in 1..48): where both pad to the same
+// width the 64-orbital direct-LDS kernels are faster (measured per
+// orbital-count class on the batch, and on 64 orbitals of the 48^3 domain).
+// In split modes only the correction takes them: the split projection's own
+// kernels were as fast or faster in every class.
+bool narrow_pays(const dcmesh_domain& d, int prec) {
+  return (narrow_ok(d, prec) || narrow_split_ok(d, prec)) && d.n_orb % 64 != 0 && d.n_orb % 64 <= 48;
+}
+
 int proj_variant(const dcmesh_domain& d, int prec) {
   int base = proj_variant_base(d, prec);
+  if (base == 8) {
+    // every orbital in one block, 64 projectors per block: FP32 launch keys
+    // 12 + 2 (NB - 1) + wide, split 8 + NB - 1; larger orbital counts and FP64
+    // run 4
+    if (narrow_ok(d, prec)) return kProjNarrow + 2 * (narrow_nb(d) - 1) + (wide_proj(d, prec) ? 1 : 0);
+    if (narrow_split_ok(d, prec)) return kSplitNarrow + narrow_nb(d) - 1;
+    base = 4;
+  }
   if (base == 7) {
     // FP32: the three-product kernel on 64 projectors x 32 complex orbitals
     // (launch keys 10 and 11: 8-byte and 16-byte loads), for any row length;
@@ -208,6 +236,14 @@ bool direct_corr_ok(const dcmesh_domain& d, int prec) {
 }
 int corr_variant(const dcmesh_domain& d, int prec) {
   int base = corr_variant_base(d, prec);
+  if (base == 7) {
+    // every orbital in one block, 64 grid rows per block: FP32 launch keys
+    // 16 + 2 (NB - 1) + wide, split 8 + NB - 1; larger orbital counts and FP64
+    // run 5
+    if (narrow_ok(d, prec)) return kCorrNarrow + 2 * (narrow_nb(d) - 1) + (wide_corr(d, prec) ? 1 : 0);
+    if (narrow_split_ok(d, prec)) return kSplitNarrow + narrow_nb(d) - 1;
+    base = 5;
+  }
   if (base == 6) {
     if (is_split(prec)) return 5;
     // FP32: the 64-complex-column direct-LDS kernel with the output tile
@@ -245,6 +281,8 @@ int proj_variant_base(const dcmesh_domain& d, int prec) {
   // back where it cannot run), 1 = 64 x 64, 2 = 64 x 128.  Split: 5 = three stages
   // on eight waves, 128 x 256; 4 and 6 = two stages, 128 x 128 and 64 x 64.
   struct Cand { int v, bm, bn; double cost; };
+  // FP32 domains whose orbitals a 64-orbital tile would pad: every orbital in one block
+  if (prec == DCMESH_FP32 && narrow_pays(d, prec)) return 8;
   static const Cand kF32[] = {{4, 128, 128, 1.0}, {5, 64, 128, 1.01}, {1, 64, 64, 1.43}, {2, 64, 128, 1.36}};
   static const Cand kSplit[] = {{5, 128, 256, 1.0}, {4, 128, 128, 1.15}, {6, 64, 64, 1.59}};
   const Cand* c = is_split(prec) ? kSplit : kF32;
@@ -261,6 +299,8 @@ int corr_variant_base(const dcmesh_domain& d, int prec) {
   const int t = tuned(DCMESH_KERNEL_CORRECT, prec, d);
   if (t >= 0) return t;
   if (is_fp64(prec)) return 2 * d.n_orb > 32 ? 0 : 2;
+  // domains whose orbitals a 64-orbital tile would pad: every orbital in one block
+  if (narrow_pays(d, prec)) return 7;
   // large tiles: both tiles loaded into LDS directly, three stages on eight waves
   if (is_split(prec)) return 2 * d.n_orb > 128 ? 5 : 1;
   const int n2 = 2 * d.n_orb;
@@ -450,9 +490,11 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     // FP32 launch key kProjDirect + 1: the direct-LDS kernel on 64 projectors x 64 complex orbitals
     const int v = pv(i);
     const GemmVariant t = is_fp64(prec)  ? kProjF64[v % 4]
-                          : is_split(prec) ? kProjSplit[v]
+                          : is_split(prec) ? (v >= kSplitNarrow ? GemmVariant{64, 32 * (v - kSplitNarrow + 1)}
+                                                                : kProjSplit[v])
                           : v == kProjDirect + 1 ? GemmVariant{64, 128}
                           : (v == 10 || v == 11) ? GemmVariant{64, 64}
+                          : v >= kProjNarrow ? GemmVariant{64, 32 * ((v - kProjNarrow) / 2 + 1)}
                                                  : kProjF32[v % 4];
     const DomDesc& D = P.desc[i];
     const size_t b0 = it.size();
@@ -476,7 +518,9 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     // 0; keys 10 and 14: on 64 complex columns
     const int v = cv(i);
     const GemmVariant t = is_fp64(prec)  ? kCorrF64[v % 4]
-                          : is_split(prec) ? kCorrSplit[v]
+                          : is_split(prec) ? (v >= kSplitNarrow ? GemmVariant{64, 32 * (v - kSplitNarrow + 1)}
+                                                                : kCorrSplit[v])
+                          : v >= kCorrNarrow ? GemmVariant{64, 32 * ((v - kCorrNarrow) / 2 + 1)}
                           : (v == 10 || v == 11 || v == 14 || v == 15) ? GemmVariant{64, 128}
                                                  : kCorrF32[v % 4];
     const DomDesc& D = P.desc[i];
@@ -899,6 +943,11 @@ void launch_project(const Ctx& c, int u_slot, int a_slot = -1) {
         case 9: k_project3m_dl<64, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 10: k_project3m<64, 32, kProjKG, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
         case 11: k_project3m<64, 32, kProjKG, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+#define DCM_PN(NB)                                                                                  \
+  case kProjNarrow + 2 * (NB - 1): k_project3m_n<NB, 2><<<g, b, 0, c.s>>>(c.d_desc, it, a); break; \
+  case kProjNarrow + 2 * (NB - 1) + 1: k_project3m_n<NB, 4><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
+        DCM_PN(1) DCM_PN(2) DCM_PN(3) DCM_PN(4) DCM_PN(5) DCM_PN(6)
+#undef DCM_PN
         default: k_project3m_dl<128, 64, kProjKG><<<g, b, 0, c.s>>>(c.d_desc, it, a); break;
       }
     } else {
@@ -941,6 +990,11 @@ void launch_correct(const Ctx& c, int out_slot) {
         case 11: k_correct3m_dl<64, 64, 16, 2, true><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 14: k_correct3m_dl<64, 64, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
         case 15: k_correct3m_dl<64, 64, 16, 4, true><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+#define DCM_CN(NB)                                                                                         \
+  case kCorrNarrow + 2 * (NB - 1): k_correct3m_n<NB, 2><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break; \
+  case kCorrNarrow + 2 * (NB - 1) + 1: k_correct3m_n<NB, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
+        DCM_CN(1) DCM_CN(2) DCM_CN(3) DCM_CN(4) DCM_CN(5) DCM_CN(6)
+#undef DCM_CN
         default: k_correct3m_dl<64, 128, 16, 4><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot); break;
       }
     } else {
@@ -998,6 +1052,10 @@ void launch_project_split(const Ctx& c, int u_slot, bool umax_known = false) {
       case 3: k_project_split<MODE, 128, 256, 16><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 4: k_project_split_dl<MODE, 128, 128><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
       case 6: k_project_split_dl<MODE, 64, 64><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+#define DCM_SPN(NB) \
+  case kSplitNarrow + NB - 1: k_project_split_n<MODE, NB><<<g, b, 0, c.s>>>(c.d_desc, it, u_slot); break;
+      DCM_SPN(1) DCM_SPN(2) DCM_SPN(3) DCM_SPN(4) DCM_SPN(5) DCM_SPN(6)
+#undef DCM_SPN
       default: k_project_split_dl3<MODE><<<g, dim3(kBlockProj3), 0, c.s>>>(c.d_desc, it, u_slot); break;
     }
   }
@@ -1024,6 +1082,10 @@ void launch_correct_split(const Ctx& c, int out_slot, bool umax = false) {
       case 2: k_correct_split<MODE, 64, 256, 64><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
       case 3: k_correct_split<MODE, 128, 256, 32><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
       case 4: k_correct_split_dl<MODE, 64, 256><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
+#define DCM_SCN(NB) \
+  case kSplitNarrow + NB - 1: k_correct_split_n<MODE, NB><<<g, b, 0, c.s>>>(c.d_desc, it, out_slot, um); break;
+      DCM_SCN(1) DCM_SCN(2) DCM_SCN(3) DCM_SCN(4) DCM_SCN(5) DCM_SCN(6)
+#undef DCM_SCN
       default: k_correct_split_dl3<MODE><<<g, dim3(kBlockCorr3), 0, c.s>>>(c.d_desc, it, out_slot, um); break;
     }
   }

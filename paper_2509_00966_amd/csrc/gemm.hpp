@@ -1014,5 +1014,256 @@ __global__ __launch_bounds__(kBlock) void k_correct3m_dl(const DomDesc* __restri
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 three-product products with every orbital of a domain in one block,
+// for domains with at most 16 NB orbitals.  Four waves are stacked along the
+// long operand's rows (16 rows each), and each wave covers all NB 16-orbital
+// column blocks, so the orbital padding stays below 16 columns: on the batch of
+// domains with 16-96 orbitals, 64-orbital tiles do 1.5x (correction) and 1.8x
+// (projection) the useful products.  Both tiles pass through registers into
+// double-buffered LDS; the loads are issued a stage ahead (the projection's,
+// over long reductions, two stages ahead in two register sets) and stay in
+// flight across the LDS-only barriers.
+// ---------------------------------------------------------------------------
+
+// Row stride (floats) of an LDS tile of 16 NB columns: consecutive rows start
+// on opposite halves of the banks for the two 16-lane quarters of a half-wave.
+template <int NB>
+constexpr int narrow_ld() { return 16 * NB + (NB % 2 == 0 ? 16 : 0); }
+
+// Correction out += B Q (Q as the three planes of qmat3) on 64-row tiles.
+// Items: (dom, 64-row tile, 0, 0).  A stage holds KC = 16 projectors.  The
+// output tile is requested before the reduction, so its latency is spent
+// under the products.
+template <int NB, int VW>
+__global__ __launch_bounds__(kBlock) void k_correct3m_n(const DomDesc* __restrict__ doms,
+                                                        const Item* __restrict__ items, int out_slot) {
+  constexpr int KC = 16, BMG = 64, BNC = 16 * NB;
+  constexpr int LA = 2 * KC + 2, LB = narrow_ld<NB>();
+  constexpr int VA = BMG * 2 * KC / VW, RA = (VA + kBlock - 1) / kBlock;
+  constexpr int VQ = 3 * KC * BNC / 4, RQ = (VQ + kBlock - 1) / kBlock;
+  __shared__ __align__(16) float sA[2][BMG * LA];
+  __shared__ __align__(16) float sB[2][3 * KC * LB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no = D.n_orb, K2 = 2 * np;
+  const long long ldq3 = D.ldq3;
+  const long long g0 = (long long)it.a * BMG;
+  const float* __restrict__ Braw = (const float*)D.proj;
+  const float* __restrict__ Q3 = (const float*)D.qmat3;
+  float* __restrict__ out = (float*)D.slot[out_slot];
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = wv * 16;
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 k1[NB], k2[NB], k3[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) k1[j] = k2[j] = k3[j] = f32x4{0, 0, 0, 0};
+  float2 prev[NB][4];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long g = g0 + wm0 + 4 * lk + r;
+      const int n = j * 16 + ll;
+      prev[j][r] = (g < D.n_grid && n < no) ? *reinterpret_cast<const float2*>(out + (g * no + n) * 2)
+                                             : make_float2(0.f, 0.f);
+    }
+
+  // one register set, loaded a stage ahead (the reductions are short: two
+  // register sets cost occupancy and measured slower)
+  Vec<float, VW> ra[1][RA];
+  Vec<float, 4> rq[1][RQ];
+  auto load = [&](int set, int st) {
+    const int p0 = st * KC;
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (2 * KC / VW), c = (idx % (2 * KC / VW)) * VW;
+      const long long g = g0 + r;
+      const int k = 2 * p0 + c;
+      ra[set][q] = (idx < VA && g < D.n_grid && k < K2) ? vload<float, VW>(Braw + g * K2 + k) : vzero<float, VW>();
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int row = idx / (BNC / 4), c = (idx % (BNC / 4)) * 4;    // row = plane * KC + projector
+      const int pl = row / KC, p = p0 + row % KC;
+      rq[set][q] = (idx < VQ && p < np && c < ldq3) ? vload<float, 4>(Q3 + ((long long)pl * np + p) * ldq3 + c)
+                                                    : vzero<float, 4>();
+    }
+  };
+  auto store = [&](int set, int b) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (2 * KC / VW), c = (idx % (2 * KC / VW)) * VW;
+#pragma unroll
+        for (int e = 0; e < VW; e += 2)
+          *reinterpret_cast<float2*>(&sA[b][r * LA + c + e]) = make_float2(ra[set][q].v[e], ra[set][q].v[e + 1]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VQ) {
+        const int row = idx / (BNC / 4), c = (idx % (BNC / 4)) * 4;
+        *reinterpret_cast<Vec<float, 4>*>(&sB[b][row * LB + c]) = rq[set][q];
+      }
+    }
+  };
+  auto compute = [&](int b) {
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int pl = 4 * ks + lk;
+      const float2 v = *reinterpret_cast<const float2*>(&sA[b][(wm0 + ll) * LA + 2 * pl]);
+      const float a1 = v.x + v.y, a2 = v.x, a3 = v.y;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int col = j * 16 + ll;
+        k1[j] = Mfma<float>::run(a1, sB[b][(0 * KC + pl) * LB + col], k1[j]);
+        k2[j] = Mfma<float>::run(a2, sB[b][(1 * KC + pl) * LB + col], k2[j]);
+        k3[j] = Mfma<float>::run(a3, sB[b][(2 * KC + pl) * LB + col], k3[j]);
+      }
+    }
+  };
+  // stage st: LDS buffer st % 2, whose last readers (stage st - 2) finished
+  // before the barrier of stage st - 1
+  const int n_st = (np + KC - 1) / KC;
+  load(0, 0);
+  for (int st = 0; st < n_st; ++st) {
+    store(0, st & 1);
+    lds_barrier();
+    if (st + 1 < n_st) load(0, st + 1);
+    compute(st & 1);
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long g = g0 + wm0 + 4 * lk + r;
+      const int n = j * 16 + ll;
+      if (g < D.n_grid && n < no)
+        *reinterpret_cast<float2*>(out + (g * no + n) * 2) =
+            make_float2(prev[j][r].x + (k1[j][r] - k3[j][r]), prev[j][r].y + (k1[j][r] + k2[j][r]));
+    }
+}
+
+// Projection partials P_split = h^3-free sum over the split's grid points of
+// conj(B) u (the h^3 and D factors are applied by k_reduce), for 64
+// projectors per block.  Items: (dom, 64-projector tile, 0, split).  A stage
+// holds KG = 16 grid points.  Waves whose 16 projectors lie past n_proj load
+// and synchronise with the others but skip their products.
+template <int NB, int VW>
+__global__ __launch_bounds__(kBlock) void k_project3m_n(const DomDesc* __restrict__ doms,
+                                                        const Item* __restrict__ items, ProjArgs args) {
+  constexpr int KG = 16, BM = 64, BNC = 16 * NB;
+  constexpr int LA = 2 * BM + 8, LB = 2 * narrow_ld<NB>();
+  constexpr int VA = KG * 2 * BM / VW, RA = (VA + kBlock - 1) / kBlock;
+  constexpr int VB = KG * 2 * BNC / VW, RB = (VB + kBlock - 1) / kBlock;
+  __shared__ __align__(16) float sA[2][KG * LA];
+  __shared__ __align__(16) float sB[2][KG * LB];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no = D.n_orb, no2 = 2 * no;
+  const float* __restrict__ Bsrc = (const float*)proj_operand<4>(D, args.a_slot);
+  const float* __restrict__ U = (const float*)D.slot[args.u_slot];
+  const int p0 = it.a * BM;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = wv * 16;
+  const bool active = p0 + wm0 < np;          // wave-uniform
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 k1[NB], k2[NB], k3[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) k1[j] = k2[j] = k3[j] = f32x4{0, 0, 0, 0};
+
+  // two register sets: stage st is loaded into set st % 2 two stages ahead
+  Vec<float, VW> ra[2][RA], rb[2][RB];
+  auto load = [&](int set, long long gc) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (2 * BM / VW), c = (idx % (2 * BM / VW)) * VW;
+      const long long g = gc + gl;
+      const int p2 = 2 * p0 + c;
+      ra[set][q] = (idx < VA && g < g_end && p2 < 2 * np) ? vload<float, VW>(Bsrc + g * (2 * np) + p2)
+                                                          : vzero<float, VW>();
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (2 * BNC / VW), c = (idx % (2 * BNC / VW)) * VW;
+      const long long g = gc + gl;
+      rb[set][q] = (idx < VB && g < g_end && c < no2) ? vload<float, VW>(U + g * no2 + c) : vzero<float, VW>();
+    }
+  };
+  auto store = [&](int set) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int gl = idx / (2 * BM / VW), c = (idx % (2 * BM / VW)) * VW;
+        *reinterpret_cast<Vec<float, VW>*>(&sA[set][gl * LA + c]) = ra[set][q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int gl = idx / (2 * BNC / VW), c = (idx % (2 * BNC / VW)) * VW;
+        *reinterpret_cast<Vec<float, VW>*>(&sB[set][gl * LB + c]) = rb[set][q];
+      }
+    }
+  };
+  auto compute = [&](int b) {
+#pragma unroll
+    for (int ks = 0; ks < KG / 4; ++ks) {
+      const int gl = 4 * ks + lk;
+      const float2 v = *reinterpret_cast<const float2*>(&sA[b][gl * LA + 2 * (wm0 + ll)]);
+      const float a1 = v.x - v.y, a2 = v.x, a3 = -v.y;   // conj(B): b' = -Im B
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const float2 w = *reinterpret_cast<const float2*>(&sB[b][gl * LB + 2 * (j * 16 + ll)]);
+        k1[j] = Mfma<float>::run(a1, w.x, k1[j]);
+        k2[j] = Mfma<float>::run(a2, w.y - w.x, k2[j]);
+        k3[j] = Mfma<float>::run(a3, w.x + w.y, k3[j]);
+      }
+    }
+  };
+  // stage st: registers and LDS buffer st % 2 (as in k_correct3m_n)
+  const int n_st = (int)((g_end - g_begin + KG - 1) / KG);
+  load(0, g_begin);
+  if (n_st > 1) load(1, g_begin + KG);
+  for (int st = 0; st < n_st; st += 2) {
+    store(0);
+    lds_barrier();
+    if (st + 2 < n_st) load(0, g_begin + (long long)(st + 2) * KG);
+    if (active) compute(0);
+    if (st + 1 >= n_st) break;
+    store(1);
+    lds_barrier();
+    if (st + 3 < n_st) load(1, g_begin + (long long)(st + 3) * KG);
+    if (active) compute(1);
+  }
+  if (!active) return;
+  float* __restrict__ part = (float*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = p0 + wm0 + 4 * lk + r;
+      const int n = j * 16 + ll;
+      if (p < np && n < no)
+        *reinterpret_cast<float2*>(&part[(long long)p * no2 + 2 * n]) =
+            make_float2(k1[j][r] - k3[j][r], k1[j][r] + k2[j][r]);
+    }
+}
+
 }  // namespace dcm
 

@@ -1139,5 +1139,257 @@ __global__ __launch_bounds__(kBlockProj3) void k_project_split_dl3(const DomDesc
       }
 }
 
+// ---------------------------------------------------------------------------
+// Split products with every orbital of a domain in one block (at most 16 NB
+// orbitals, 32 NB real columns), as the FP32 kernels of the same name: four
+// waves stacked along the long operand's rows, 16 rows each, every wave over
+// all 2 NB 16-column blocks.  Registers are loaded a stage ahead into
+// double-buffered LDS, one LDS-only barrier per stage.
+// ---------------------------------------------------------------------------
+
+// out[g][j] += sum_k Bs[g][k] Qt[j][k], 64 grid rows per block.  Items: (dom,
+// 64-row tile, 0, 0).  KC = 32 reduction indices per stage.
+template <int MODE, int NB>
+__global__ __launch_bounds__(kBlock) void k_correct_split_n(const DomDesc* __restrict__ doms,
+                                                            const Item* __restrict__ items, int out_slot, int umax) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int KC = 32, LK = KC + 8, BMG = 64, BN = 32 * NB, TN = 2 * NB;
+  constexpr int VA = BMG * KC / 8, VB = BN * KC / 8;
+  constexpr int RA = (VA + kBlock - 1) / kBlock, RB = (VB + kBlock - 1) / kBlock;
+  __shared__ __align__(16) T sAh[2][BMG * LK], sAl[2][BMG * LK];
+  __shared__ __align__(16) T sBh[2][BN * LK], sBl[2][BN * LK];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const long long ldbs = D.ldbs, ldqt = D.ldqt;
+  const int no2 = 2 * D.n_orb;
+  const long long g0 = (long long)it.a * BMG;
+  const T* __restrict__ ah_g = (const T*)D.bs_hi;
+  const T* __restrict__ al_g = (const T*)D.bs_lo;
+  const T* __restrict__ bh_g = (const T*)D.qt_hi;
+  const T* __restrict__ bl_g = (const T*)D.qt_lo;
+  float* __restrict__ out = (float*)D.slot[out_slot];
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = wv * 16;
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 acc[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) acc[j] = f32x4{0, 0, 0, 0};
+  // the output tile, requested before the reduction
+  float prev[TN][4];
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long g = g0 + wm0 + 4 * lk + r;
+      const int jj = j * 16 + ll;
+      prev[j][r] = (g < D.n_grid && jj < no2) ? out[g * no2 + jj] : 0.f;
+    }
+
+  V8 rah[RA], ral[RA], rbh[RB], rbl[RB];
+  const V8 z8 = {};
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
+      const long long g = g0 + r;
+      const int k = k0 + c;
+      const bool ok = idx < VA && g < D.n_grid && k < ldbs;
+      rah[q] = ok ? *(const V8*)(ah_g + g * ldbs + k) : z8;
+      ral[q] = ok ? *(const V8*)(al_g + g * ldbs + k) : z8;
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
+      const int k = k0 + c;
+      const bool ok = idx < VB && r < no2 && k < ldqt;
+      rbh[q] = ok ? *(const V8*)(bh_g + (long long)r * ldqt + k) : z8;
+      rbl[q] = ok ? *(const V8*)(bl_g + (long long)r * ldqt + k) : z8;
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
+        *(V8*)&sAh[b][r * LK + c] = rah[q];
+        *(V8*)&sAl[b][r * LK + c] = ral[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int r = idx / (KC / 8), c = (idx % (KC / 8)) * 8;
+        *(V8*)&sBh[b][r * LK + c] = rbh[q];
+        *(V8*)&sBl[b][r * LK + c] = rbl[q];
+      }
+    }
+  };
+  auto compute = [&](int b) {
+    const int oa = (wm0 + ll) * LK + 8 * lk;
+    const V8 ah = *(const V8*)&sAh[b][oa], al = *(const V8*)&sAl[b][oa];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int o = (j * 16 + ll) * LK + 8 * lk;
+      const V8 bh = *(const V8*)&sBh[b][o], bl = *(const V8*)&sBl[b][o];
+      acc[j] = Half<MODE>::mma(ah, bh, acc[j]);
+      acc[j] = Half<MODE>::mma(ah, bl, acc[j]);
+      acc[j] = Half<MODE>::mma(al, bh, acc[j]);
+    }
+  };
+  // stage st: LDS buffer st % 2, whose last readers (stage st - 2) finished
+  // before the barrier of stage st - 1
+  const int n_st = (int)(ldbs / KC);   // ldbs: a multiple of 32, zero padded
+  load(0);
+  for (int st = 0; st < n_st; ++st) {
+    store(st & 1);
+    lds_barrier();
+    if (st + 1 < n_st) load((st + 1) * KC);
+    compute(st & 1);
+  }
+  const float unscale = MODE == 1 ? 1.0f / (fp16_scale_from_bits(D.maxbits[0]) * fp16_scale_from_bits(D.maxbits[2]))
+                                  : 1.0f;
+  float vmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long g = g0 + wm0 + 4 * lk + r;
+      const int jj = j * 16 + ll;
+      if (g < D.n_grid && jj < no2) {
+        const float v = prev[j][r] + acc[j][r] * unscale;
+        out[g * no2 + jj] = v;
+        vmax = fmaxf(vmax, fabsf(v));
+      }
+    }
+  if (MODE == 1 && umax) wave_umax(D, vmax);
+}
+
+// Projection partials from Bt (pre-split) and u (split while staged), 64
+// projectors per block.  Items: (dom, 64-projector tile, 0, split).  KG = 16
+// grid points (32 reduction indices) per stage.  Waves whose 16 projectors
+// lie past n_proj load and synchronise but skip their products.
+template <int MODE, int NB>
+__global__ __launch_bounds__(kBlock) void k_project_split_n(const DomDesc* __restrict__ doms,
+                                                            const Item* __restrict__ items, int u_slot) {
+  using T = typename Half<MODE>::T;
+  using V8 = typename Half<MODE>::V8;
+  constexpr int KG = 16, KK = 2 * KG, LK = KK + 8, BM = 64, BN = 32 * NB, TN = 2 * NB;
+  constexpr int VA = BM * KK / 8, RA = (VA + kBlock - 1) / kBlock;
+  constexpr int VB = KG * BN / 2, RB = (VB + kBlock - 1) / kBlock;
+  __shared__ __align__(16) T sAh[2][BM * LK], sAl[2][BM * LK];
+  __shared__ __align__(16) T sBh[2][BN * LK], sBl[2][BN * LK];
+
+  const Item it = items[blockIdx.x];
+  const DomDesc& D = doms[it.dom];
+  const int np = D.n_proj, no2 = 2 * D.n_orb;
+  const long long ldbt = D.ldbt;
+  const int p0 = it.a * BM;
+  const long long g_begin = (long long)it.c * D.split_len;
+  const long long g_end = min(g_begin + (long long)D.split_len, D.n_grid);
+  const float2* __restrict__ U = (const float2*)D.slot[u_slot];
+  const T* __restrict__ bth = (const T*)D.bt_hi;
+  const T* __restrict__ btl = (const T*)D.bt_lo;
+  const float su = MODE == 1 ? fp16_scale_from_bits(D.maxbits[1]) : 1.0f;
+  const float sbs = MODE == 1 ? fp16_scale_from_bits(D.maxbits[0]) : 1.0f;
+
+  const int lane = threadIdx.x % kWave, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wm0 = wv * 16;
+  const bool active = p0 + wm0 < np;      // wave-uniform
+  const int ll = lane % 16, lk = lane / 16;
+  f32x4 acc[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) acc[j] = f32x4{0, 0, 0, 0};
+
+  V8 rah[RA], ral[RA];
+  float2 rb[RB];
+  const V8 z8 = {};
+  auto load = [&](long long gc) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int r = idx / (KK / 8), c = (idx % (KK / 8)) * 8;
+      const int p = p0 + r;
+      const long long k = 2 * gc + c;
+      const bool ok = idx < VA && p < np && k < 2 * g_end;   // rows are zero padded to ldbt
+      rah[q] = ok ? *(const V8*)(bth + (long long)p * ldbt + k) : z8;
+      ral[q] = ok ? *(const V8*)(btl + (long long)p * ldbt + k) : z8;
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+      const long long g = gc + gl;
+      rb[q] = (idx < VB && g < g_end && 2 * nn < no2) ? U[g * (no2 / 2) + nn] : make_float2(0.f, 0.f);
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VA) {
+        const int r = idx / (KK / 8), c = (idx % (KK / 8)) * 8;
+        *(V8*)&sAh[b][r * LK + c] = rah[q];
+        *(V8*)&sAl[b][r * LK + c] = ral[q];
+      }
+    }
+    // column j, k = 2 g_local + c: c = 0 -> u[g][j]; c = 1 -> (j even: u[g][j+1],
+    // j odd: -u[g][j-1]), one 4-byte pair per plane and column
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int idx = threadIdx.x + q * kBlock;
+      if (idx < VB) {
+        const int gl = idx / (BN / 2), nn = idx % (BN / 2);
+        T rh, rl, ih, il;
+        split2<MODE>(rb[q].x, su, rh, rl);
+        split2<MODE>(rb[q].y, su, ih, il);
+        const T nrh = (T)(-(float)rh), nrl = (T)(-(float)rl);
+        const int c0 = (2 * nn) * LK + 2 * gl, c1 = (2 * nn + 1) * LK + 2 * gl;
+        *(Pair<T>*)&sBh[b][c0] = Pair<T>{rh, ih};
+        *(Pair<T>*)&sBh[b][c1] = Pair<T>{ih, nrh};
+        *(Pair<T>*)&sBl[b][c0] = Pair<T>{rl, il};
+        *(Pair<T>*)&sBl[b][c1] = Pair<T>{il, nrl};
+      }
+    }
+  };
+  auto compute = [&](int b) {
+    const int oa = (wm0 + ll) * LK + 8 * lk;
+    const V8 ah = *(const V8*)&sAh[b][oa], al = *(const V8*)&sAl[b][oa];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int o = (j * 16 + ll) * LK + 8 * lk;
+      const V8 bh = *(const V8*)&sBh[b][o], bl = *(const V8*)&sBl[b][o];
+      acc[j] = Half<MODE>::mma(ah, bh, acc[j]);
+      acc[j] = Half<MODE>::mma(ah, bl, acc[j]);
+      acc[j] = Half<MODE>::mma(al, bh, acc[j]);
+    }
+  };
+  const int n_st = (int)((g_end - g_begin + KG - 1) / KG);
+  load(g_begin);
+  for (int st = 0; st < n_st; ++st) {
+    store(st & 1);
+    lds_barrier();
+    if (st + 1 < n_st) load(g_begin + (long long)(st + 1) * KG);
+    if (active) compute(st & 1);
+  }
+  if (!active) return;
+  const float unscale = 1.0f / (su * sbs);
+  float* __restrict__ part = (float*)D.ppart + (long long)it.c * np * no2;
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = p0 + wm0 + 4 * lk + r;
+      const int jj = j * 16 + ll;
+      if (p < np && jj < no2) part[(long long)p * no2 + jj] = acc[j][r] * unscale;
+    }
+}
+
 }  // namespace dcm
 

@@ -91,18 +91,6 @@ __device__ __forceinline__ void halo_xy(int hidx, int& lx, int& ly) {
   }
 }
 
-// Barrier of the LDS plane exchange in the z sweeps: waits for this wave's
-// own LDS reads and writes (lgkmcnt(0)), then for the other waves.  Global
-// loads stay in flight across it: a __syncthreads() fence would also wait for
-// every prefetch of later planes, draining the memory pipeline once per plane.
-// The registers those loads fill are waited for where they are used.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
 // Items: (dom, x tile, y tile, (z segment << 16) | orbital chunk).
 // D.zseg planes per segment.  Energy partials: one per item, at
 // e_loc[blockIdx.x - D.item0_stencil].  Density partials at

@@ -323,15 +323,17 @@ def test_every_z_segment_choice_matches_oracle(api, zseg):
                                                 ((16, 16, 16), 64, 8),      # whole stages, 64 projectors
                                                 ((17, 15, 9), 21, 2),       # odd N_o
                                                 ((12, 11, 10), 130, 3)])    # two orbital tiles
-@pytest.mark.parametrize("family,variant", [("project", 4), ("project", 5), ("project", 7), ("correct", 4),
-                                            ("correct", 5), ("correct", 6)])
+@pytest.mark.parametrize("family,variant", [("project", 4), ("project", 5), ("project", 7), ("project", 8),
+                                            ("correct", 4), ("correct", 5), ("correct", 6), ("correct", 7)])
 def test_direct_lds_products_match_oracle(api, family, variant, shape, n_orb, n_atoms):
     """The FP32 projection / correction with tiles loaded straight into LDS
     (tuning variant 4 of each family; variant 5: the projection on 64
     projectors, the correction on 64 complex columns; correction variant 6:
     as 5 with the output tile requested before the reduction; projection
     variant 7: the three-product kernel through registers on 64 x 32, with
-    8-byte loads for odd orbital counts), two steps against the oracle."""
+    8-byte loads for odd orbital counts; projection variant 8 and correction
+    variant 7: every orbital in one block, or the 64-column kernels past 96
+    orbitals), two steps against the oracle."""
     torch = _torch()
     dom = make_domain(43, shape, n_orb, n_atoms, proj_per_atom=8, h=0.4, fd_order=6)
     a_mid = _field(2)
@@ -358,3 +360,30 @@ def test_check_finite_flags_nan(api):
     with pytest.raises(DcmeshError) as ei:
         api.step([g], a_tensor(_field(1)), 0.02, 1, "fp32", ws, check_finite=True)
     assert ei.value.code == 5
+
+
+@pytest.mark.parametrize("family,variant", [("project", 8), ("correct", 7)])
+def test_narrow_products_every_width(api, family, variant):
+    """The FP32 products with every orbital of a domain in one block, at each
+    of their widths (16 NB orbitals, NB = 1..6: 9, 17, 40, 55, 70 and 96
+    orbitals, odd and even, so both load widths run) in one batched call;
+    24 and 72 projectors leave projection waves with no projectors (they
+    skip their products); two steps against the oracle per domain."""
+    torch = _torch()
+    spec = [((11, 10, 9), 9, 3), ((12, 11, 10), 17, 3), ((10, 12, 11), 40, 9), ((9, 11, 12), 55, 3),
+            ((11, 11, 11), 70, 9), ((10, 10, 12), 96, 12)]
+    doms = [make_domain(120 + i, shp, no, na, proj_per_atom=8, h=0.4, fd_order=6)
+            for i, (shp, no, na) in enumerate(spec)]
+    a_mid = _field(2)
+    gs = [to_device(d, "fp32") for d in doms]
+    ws = api.Workspace.for_domains(gs, "fp32")
+    try:
+        api.set_tuning(family, variant)
+        api.step(gs, a_tensor(a_mid), 0.02, 2, "fp32", ws)
+        torch.cuda.synchronize()
+    finally:
+        api.set_tuning(family, -1)
+    for d, g in zip(doms, gs):
+        od = oracle_inputs(d, "fp32")
+        ref, _ = P.propagate(od, a_mid, 0.02, od.psi)
+        assert_close(_np(g.psi), ref, TOL_PSI["fp32"], label=f"N_o={d.n_orb} N_p={d.n_proj}")

@@ -33,12 +33,13 @@ def _dom(seed=51):
     return make_domain(seed, (19, 13, 21), 21, 3, proj_per_atom=8, h=0.4, fd_order=6)
 
 
-@pytest.mark.parametrize("corr_variant", [-1, 0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("corr_variant", [-1, 0, 1, 2, 3, 4, 5, 7])
 @pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
 def test_split_hpsi_matches_split_reference(api, precision, mode, corr_variant):
     """Every correction tile variant (4 and 5: both tiles loaded into LDS
-    directly, two-stage on four waves and three-stage on eight); 21 orbitals
-    and 24 projectors leave partial tiles in both dimensions."""
+    directly, two-stage on four waves and three-stage on eight; 7: every
+    orbital in one block); 21 orbitals and 24 projectors leave partial tiles
+    in both dimensions."""
     import torch
     dom = _dom()
     A = np.array([0.05, -0.11, 0.23])
@@ -62,7 +63,7 @@ def test_split_hpsi_matches_split_reference(api, precision, mode, corr_variant):
     assert_close(_np(hp), exact, (2e-4 if mode == "bf16" else 2e-5))
 
 
-@pytest.mark.parametrize("corr_variant", [4, 5])
+@pytest.mark.parametrize("corr_variant", [4, 5, 7])
 @pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
 def test_split_correction_stage_counts(api, precision, mode, corr_variant):
     """The correction kernels that load both tiles into LDS directly, over
@@ -89,12 +90,12 @@ def test_split_correction_stage_counts(api, precision, mode, corr_variant):
         assert_close(_np(hp[i]), ref, fp32_operator_tol(od, A, od.psi, ref), label=str(i))
 
 
-@pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("proj_variant", [0, 1, 2, 3, 4, 5, 6, 8])
 @pytest.mark.parametrize("precision,mode", [("split_bf16", "bf16"), ("split_fp16", "fp16")])
 def test_split_projection_variants_match_split_reference(api, precision, mode, proj_variant):
     """Every projection tile variant (4, 5 and 6: the projector planes loaded
     into LDS directly, two-stage 128 x 128, three-stage 128 x 256, two-stage
-    64 x 64) on
+    64 x 64; 8: every orbital in one block, 64 projectors) on
     three domains: 24 projectors / 21 orbitals (one partial tile), 136
     projectors / 70 orbitals (a second tile in both dimensions with a ragged
     edge) and a 100-point grid (seven 16-point stages, fewer than one turn of
