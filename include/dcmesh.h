@@ -291,17 +291,23 @@ int dcmesh_graph_destroy(void* graph);
  * (DCMESH_KERNEL_*) and value (see dcmesh_tuning_options); -1 restores the
  * built-in heuristic.  Process-wide; takes effect for calls made afterwards.
  * DCMESH_KERNEL_ZSEG picks the z-segment length of the stencil sweep (0: from
- * the block count; 1..4: 8, 16, 32 planes, whole columns).  The workspace size
- * does not depend on these choices. */
+ * the block count; 1..4: 8, 16, 32 planes, whole columns).
+ * DCMESH_KERNEL_SORDER picks the order of the stencil's work-groups (0: each
+ * domain's orbital chunks dealt over the 8 XCDs; 1, 2: each (domain, z
+ * segment) on one XCD, tiles before chunks or chunks before tiles; built in:
+ * 1 for a launch of 8 or more (domain, z segment) pairs, else 0).  The
+ * workspace size does not depend on these choices, and results do not depend
+ * on the order. */
 enum dcmesh_kernel { DCMESH_KERNEL_STENCIL = 0, DCMESH_KERNEL_PROJECT = 1, DCMESH_KERNEL_CORRECT = 2,
-                     DCMESH_KERNEL_ZSEG = 3 };
+                     DCMESH_KERNEL_ZSEG = 3, DCMESH_KERNEL_SORDER = 4 };
 int dcmesh_set_tuning(int32_t kernel, int32_t variant);
 int dcmesh_tuning_options(int32_t kernel, int32_t* count);
 
 /* Per-shape tile choices, the table an autotuner fills (not in the paper):
  * domains of exactly shape's nx, ny, nz, fd_order, n_orb and n_proj (its
  * pointers are not read) in this precision use this variant of the kernel
- * family (values as dcmesh_set_tuning; the z segment is not per shape);
+ * family (values as dcmesh_set_tuning; the z segment and the stencil work
+ * order are not per shape);
  * -1 removes the entry.  A global dcmesh_set_tuning choice takes precedence;
  * shapes without an entry use the built-in rules.  Process-wide; for calls
  * made afterwards.  dcmesh_clear_tuning_shapes empties the table. */

@@ -22,7 +22,7 @@ FLAG_CHECK_FINITE = 0x1
 FLAG_PROFILE = 0x2
 FLAG_EQ2 = 0x4
 FAMILIES = ("stencil", "project", "reduce", "correct", "density", "energy", "adjoint", "overlap", "split")
-KERNEL = {"stencil": 0, "project": 1, "correct": 2, "zseg": 3}
+KERNEL = {"stencil": 0, "project": 1, "correct": 2, "zseg": 3, "sorder": 4}
 
 EXPORTS = (
     "dcmesh_workspace_bytes", "dcmesh_step", "dcmesh_step_noalloc", "dcmesh_step_eq2", "dcmesh_density", "dcmesh_occupations",

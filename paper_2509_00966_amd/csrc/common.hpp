@@ -68,7 +68,6 @@ struct DomDesc {
   int split_len;                // grid points per split
   int zseg;                     // z planes per stencil sweep segment
   int n_e_loc, n_e_nl, n_g_part;
-  int item0_stencil;            // first item of this domain in its stencil launch
   int item0_reduce;             // ... in its reduce launch
   int item0_elem;               // ... in its elementwise launch
   int n_chunks;                 // orbital chunks of the stencil sweep

@@ -91,9 +91,18 @@ __device__ __forceinline__ void halo_xy(int hidx, int& lx, int& ly) {
   }
 }
 
+// Slot of an item's local-energy partial in D.e_loc: its index in the
+// domain's (z segment, orbital chunk, y tile, x tile) order, whatever the
+// position of the item in its launch.
+template <int TX, int TY>
+__device__ __forceinline__ int e_loc_slot(const DomDesc& D, const Item& it) {
+  const int nxt = (D.nx + TX - 1) / TX, nyt = (D.ny + TY - 1) / TY;
+  return (((it.c >> 16) * D.n_chunks + (it.c & 0xffff)) * nyt + it.b) * nxt + it.a;
+}
+
 // Items: (dom, x tile, y tile, (z segment << 16) | orbital chunk).
 // D.zseg planes per segment.  Energy partials: one per item, at
-// e_loc[blockIdx.x - D.item0_stencil].  Density partials at
+// e_loc[e_loc_slot].  Density partials at
 // dpart[chunk][g][0..3] (rho, j_x, j_y, j_z without the A rho term).
 template <typename T, int R, int OC, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_stencil_sweep(const DomDesc* __restrict__ doms,
@@ -259,7 +268,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep(const DomDesc* __restrict_
   }
   if (args.want_energy) {
     const double s = block_sum<double, NT / kWave>(e_acc, red);
-    if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+    if (threadIdx.x == 0) D.e_loc[e_loc_slot<TX, TY>(D, it)] = s;
   }
 }
 
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep2(const DomDesc* __restrict
   }
   if (args.want_energy) {
     const double s = block_sum<double, NT / kWave>(e_acc, red);
-    if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+    if (threadIdx.x == 0) D.e_loc[e_loc_slot<TX, TY>(D, it)] = s;
   }
 }
 
@@ -622,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep3(const DomDesc* __restrict
   }
   if (args.want_energy) {
     const double s = block_sum<double, NT / kWave>(e_acc, red);
-    if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+    if (threadIdx.x == 0) D.e_loc[e_loc_slot<TX, TY>(D, it)] = s;
   }
 }
 
@@ -810,7 +819,7 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
   with_phases(run, std::make_integer_sequence<int, U>{});
   if (args.want_energy) {
     const double s = block_sum<double, NT / kWave>(e_acc, red);
-    if (threadIdx.x == 0) D.e_loc[blockIdx.x - D.item0_stencil] = s;
+    if (threadIdx.x == 0) D.e_loc[e_loc_slot<TX, TY>(D, it)] = s;
   }
 }
 

@@ -99,11 +99,16 @@ def test_adjoint_and_density_argument_checks():
 def test_tuning_options():
     L = _lib()
     n = ctypes.c_int32(0)
-    for k in (0, 1, 2):
+    for k in (0, 1, 2, 3, 4):
         assert L.lib.dcmesh_tuning_options(k, ctypes.byref(n)) == 0 and n.value >= 2
         assert L.lib.dcmesh_set_tuning(k, n.value) == 1
         assert L.lib.dcmesh_set_tuning(k, -1) == 0
+    assert L.lib.dcmesh_tuning_options(4, ctypes.byref(n)) == 0 and n.value == 3
     assert L.lib.dcmesh_tuning_options(9, ctypes.byref(n)) == 1
+    # the z segment and the stencil order are process-wide only
+    shape = _dom(L)
+    for k in (3, 4):
+        assert L.lib.dcmesh_set_tuning_shape(k, 1, shape, 0) == 1
 
 
 def test_workspace_grows_with_problem():
@@ -135,7 +140,7 @@ def test_workspace_size_does_not_depend_on_tuning(precision):
     n = ctypes.c_int32(0)
     try:
         base = size()
-        for k in range(4):
+        for k in range(5):
             assert L.lib.dcmesh_tuning_options(k, ctypes.byref(n)) == 0
             for v in range(n.value):
                 assert L.lib.dcmesh_set_tuning(k, v) == 0

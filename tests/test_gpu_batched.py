@@ -99,3 +99,44 @@ def test_autotuner_choice_runs_and_agrees(doms, tmp_path):
         od = oracle_inputs(d, "fp32")
         ref, _ = P.propagate(od, a_mid, 0.02, od.psi)
         assert_close(g.psi.cpu().numpy(), ref, 1e-5)
+
+
+@pytest.mark.parametrize("zseg", [-1, 2])
+def test_stencil_work_orders_give_identical_results(doms, zseg):
+    """Every stencil work order (each domain's orbital chunks dealt over the
+    XCDs; each (domain, z segment) on one XCD, tiles before chunks or chunks
+    before tiles) gives the same psi, rho, j and E bit for bit: the order moves
+    work-groups, not arithmetic (the energy partials sit at the item's own slot
+    in its domain).  zseg 2: 16-plane segments, so most domains have several."""
+    import torch
+    import paper_2509_00966_amd as api
+    a_mid = pulse_midpoints(100, 0.02, 100)[:2]
+    at = a_tensor(a_mid)
+    runs = []
+    try:
+        api.set_tuning("zseg", zseg)
+        for order in range(api.tuning_options("sorder")):
+            api.set_tuning("sorder", order)
+            gs = [to_device(d, "fp32") for d in doms]
+            ws = api.Workspace.for_domains(gs, "fp32")
+            obs = [{"rho": torch.empty(2, d.n_grid, device="cuda"), "j": torch.empty(2, d.n_grid, 3, device="cuda"),
+                    "energy": torch.empty(2, dtype=torch.float64, device="cuda")} for d in gs]
+            api.step(gs, at, 0.02, 2, "fp32", ws, obs=obs)
+            torch.cuda.synchronize()
+            runs.append((gs, obs))
+    finally:
+        api.set_tuning("sorder", -1)
+        api.set_tuning("zseg", -1)
+    g0, o0 = runs[0]
+    for order, (gs, obs) in enumerate(runs[1:], 1):
+        for i, (a, b) in enumerate(zip(g0, gs)):
+            assert torch.equal(a.psi, b.psi), (order, i)
+        for i, (a, b) in enumerate(zip(o0, obs)):
+            for k in ("rho", "j", "energy"):
+                assert torch.equal(a[k], b[k]), (order, i, k)
+    # and the first order agrees with the oracle's energy on the first domain
+    d = doms[0]
+    od = oracle_inputs(d, "fp32")
+    _, ob = P.propagate(od, a_mid, 0.02, od.psi, want_energy=True)
+    e = o0[0]["energy"].cpu().numpy()
+    assert np.abs(e - ob["energy"]).max() < 1e-5 * np.abs(ob["energy"]).max()
