@@ -649,7 +649,7 @@ __device__ __forceinline__ void with_phases(F&& f, std::integer_sequence<int, Ps
   f(std::integral_constant<int, Ps>{}...);
 }
 
-template <typename T, int R, int OC, int TX, int TY, int NT, int GM, bool HB>
+template <typename T, int R, int OC, int TX, int TY, int NT, int GM, bool HB, bool EN>
 __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, const StencilArgs& args,
                                             const StencilW<T>& w, Cplx<T>* lds, double* red) {
   using C = Cplx<T>;
@@ -793,7 +793,7 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
         }
       }
       if (ok[k]) {
-        if (args.want_energy) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
+        if constexpr (EN) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
         if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
         C b = base_is_u ? c0 : C{0, 0};
         if constexpr (HB) b = bq[k][P % 2];
@@ -817,7 +817,7 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
       if (!(plane_step(PCs, z + decltype(PCs)::value) && ...)) break;
   };
   with_phases(run, std::make_integer_sequence<int, U>{});
-  if (args.want_energy) {
+  if constexpr (EN) {
     const double s = block_sum<double, NT / kWave>(e_acc, red);
     if (threadIdx.x == 0) D.e_loc[e_loc_slot<TX, TY>(D, it)] = s;
   }
@@ -836,19 +836,29 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict
   const DomDesc& D = doms[it.dom];
   const StencilW<T> w = stencil_weights<T>(D, args.step);
   const bool hb = args.base_slot < SLOT_NONE && args.base_slot != args.u_slot;
-  auto body = [&](auto hbc) {
-    constexpr bool HB = decltype(hbc)::value;
+  // The energy flag is a template argument: as a run-time flag the compiler
+  // evaluates every point's FP64 energy term and discards it with a select.
+  // The twelve bodies are forced inline: left to itself the compiler outlines
+  // them as calls with a private stack.
+  auto body = [&](auto hbc, auto enc) __attribute__((always_inline)) {
+    constexpr bool HB = decltype(hbc)::value, EN = decltype(enc)::value;
     if (args.want_density || w.A[0] != (T)0 || w.A[1] != (T)0)
-      sweep4_body<T, R, OC, TX, TY, NT, 7, HB>(D, it, args, w, lds, red);
+      sweep4_body<T, R, OC, TX, TY, NT, 7, HB, EN>(D, it, args, w, lds, red);
     else if (w.A[2] != (T)0)
-      sweep4_body<T, R, OC, TX, TY, NT, 4, HB>(D, it, args, w, lds, red);
+      sweep4_body<T, R, OC, TX, TY, NT, 4, HB, EN>(D, it, args, w, lds, red);
     else
-      sweep4_body<T, R, OC, TX, TY, NT, 0, HB>(D, it, args, w, lds, red);
+      sweep4_body<T, R, OC, TX, TY, NT, 0, HB, EN>(D, it, args, w, lds, red);
+  };
+  auto with_en = [&](auto hbc) __attribute__((always_inline)) {
+    if (args.want_energy)
+      body(hbc, std::true_type{});
+    else
+      body(hbc, std::false_type{});
   };
   if (hb)
-    body(std::true_type{});
+    with_en(std::true_type{});
   else
-    body(std::false_type{});
+    with_en(std::false_type{});
 }
 
 // rho[g] = sum_chunks dpart[c][g][0];  j[g][d] = sum_chunks dpart[c][g][1 + d] + A_d rho.
