@@ -62,19 +62,23 @@ size_t real_size(int prec) { return is_fp64(prec) ? 8 : 4; }
 // ---------------------------------------------------------------------------
 struct StencilVariant { int oc, tx, ty, nt; };
 // variants 6 and 7 prefetch two planes ahead with a double-buffered LDS plane
-// variants 8-11 fetch each plane's halo with its interior: 8 with the queues
-// shifted per plane (k_stencil_sweep3), 9-11 with unrolled register rings
-// (k_stencil_sweep4)
+// variants 8-12 fetch each plane's halo with its interior: 8 with the queues
+// shifted per plane (k_stencil_sweep3), 9-12 with unrolled register rings
+// (k_stencil_sweep4); FP32 variant 12 runs the 8 x 8 tile on 16 waves, one
+// column per thread (FP64 runs it as 11)
 const StencilVariant kStencilF32[] = {{16, 16, 8, 256}, {8, 16, 8, 256}, {16, 8, 8, 256},
                                       {4, 16, 16, 256}, {16, 8, 8, 512}, {16, 16, 8, 512},
                                       {16, 8, 8, 512}, {16, 8, 8, 256}, {16, 8, 8, 512},
-                                      {16, 8, 8, 512}, {16, 8, 8, 256}, {16, 16, 8, 512}};
+                                      {16, 8, 8, 512}, {16, 8, 8, 256}, {16, 16, 8, 512},
+                                      {16, 8, 8, 1024}};
 const StencilVariant kStencilF64[] = {{8, 16, 8, 256}, {8, 8, 8, 256}, {4, 16, 8, 256},
                                       {16, 8, 4, 256}, {8, 8, 8, 512}, {8, 16, 8, 512},
                                       {8, 8, 8, 512}, {8, 8, 8, 256}, {8, 8, 8, 512},
-                                      {8, 8, 8, 512}, {8, 8, 8, 256}, {8, 16, 8, 512}};
-constexpr int kNStencil = 12;
+                                      {8, 8, 8, 512}, {8, 8, 8, 256}, {8, 16, 8, 512},
+                                      {8, 16, 8, 512}};
+constexpr int kNStencil = 13;
 constexpr int kFirstSweep3 = 8;
+constexpr int kFirstSweep4 = 9;   // variants 9-12: the ring sweep (k_stencil_sweep4)
 constexpr int kStencilFallback = 2;
 constexpr int kStencilDefaultF32 = 11;   // measured best at 64^3 / 128 orbitals
 constexpr int kStencilDefaultF64 = 2;    // the 16-wide FP64 ring sweep spills
@@ -136,15 +140,20 @@ int tuned(int kernel, int prec, const dcmesh_domain& d) {
 
 // The sweep3 variants address a plane of u with 32-bit byte offsets; a domain
 // whose plane spans 2^32 bytes or more uses the default sweep instead.
-// FP32 default: the 16 x 8 column tile, or the 8 x 8 sweep of the same kind
-// (variant 9) where the wider tile pads the x edge enough to outweigh the
-// narrower tile's larger halo share (time per useful point 1.15x, measured on
-// batches of equal small domains).
+// FP32 default: the 8 x 8 sweep on 16 waves, one column per thread
+// (variant 12), for domains of x and y edges up to 40, and for larger ones
+// where the 16 x 8 tile pads the x edge enough to outweigh the narrower
+// tile's larger halo share (1.15x per useful point); else the 16 x 8 tile on
+// 8 waves.  On the batch of 512 domains with edges 20-40 the 16-wave sweep is
+// 3.4% faster than the 8-wave 8 x 8 and 16 x 8 sweeps it replaced; on the
+// 64^3 domain it takes two rounds of blocks (one 16-wave block per CU) and is
+// 3% slower than the 16 x 8 tile.
 int stencil_default_f32(const dcmesh_domain& d) {
   auto waste = [&](int tx, int ty) {
     return (double)(cdiv(d.nx, tx) * tx) * (double)(cdiv(d.ny, ty) * ty) / ((double)d.nx * d.ny);
   };
-  return 1.15 * waste(8, 8) < waste(16, 8) ? 9 : kStencilDefaultF32;
+  if (d.nx <= 40 && d.ny <= 40) return 12;
+  return 1.15 * waste(8, 8) < waste(16, 8) ? 12 : kStencilDefaultF32;
 }
 int stencil_variant(const dcmesh_domain& d, int prec) {
   const int t = tuned(DCMESH_KERNEL_STENCIL, prec, d);
@@ -366,6 +375,9 @@ struct Plan {
   size_t bytes_tables = 0, bytes_total = 0;
   size_t off_items = 0, off_flag = 0;
   bool any_proj = false;
+  // the adjoint's gradient partials come from its stencil sweeps (every
+  // domain on a ring-sweep variant, FP32 or split); else from k_grad_partial
+  bool grad_fused = false;
 };
 
 // Elements per thread of the elementwise kernels.
@@ -596,6 +608,10 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
                [&](int i, int first) { P.desc[i].item0_elem = first; });
   for (const Launch& L : P.elem)
     for (int k = 0; k < L.count; ++k) P.desc[P.items[L.first + k].dom].n_g_part++;
+  P.grad_fused = !is_fp64(prec);
+  for (int i = 0; i < n_dom; ++i) P.grad_fused &= (sv(i) % 16) >= kFirstSweep4;
+  if (P.grad_fused)
+    for (int i = 0; i < n_dom; ++i) P.desc[i].n_g_part = P.desc[i].n_e_loc;
   group_launch(P.dfinish, P.items, n_dom, [](int) { return 0; }, [&](int i, std::vector<Item>& it) {
     for (long long b = 0; b < cdiv(P.desc[i].n_grid, kBlock); ++b) it.push_back({i, (int)b, 0, 0});
   });
@@ -693,7 +709,10 @@ void build_plan(Plan& P, const dcmesh_domain* doms, int n_dom, int prec, char* w
     D.qmat3 = as_global(prec == DCMESH_FP32 ? take(3 * (size_t)D.n_proj * D.ldq3 * sizeof(float)) : (char*)nullptr);
     D.e_loc = as_global((double*)take(sizeof(double) * (size_t)std::max<long long>(D.n_e_loc, stencil_bound(D))));
     D.e_nl = as_global((double*)take(sizeof(double) * std::max(1, D.n_e_nl)));
-    D.g_part = as_global((double*)take(3 * sizeof(double) * std::max(1, D.n_g_part)));
+    // gradient partials: one per elementwise item, or one per stencil item when
+    // the sweeps form them; room for either, whatever the tile variant
+    const long long g_room = std::max<long long>(cdiv(D.n_grid * D.n_orb, (long long)kBlock * kEPT), stencil_bound(D));
+    D.g_part = as_global((double*)take(3 * sizeof(double) * (size_t)std::max<long long>(1, g_room)));
     // sized for the smallest orbital chunk of any stencil variant, so the
     // workspace does not depend on the tile choice
     D.dpart = as_global(take((size_t)cdiv(D.n_orb, 4) * D.n_grid * 4 * rs));
@@ -925,6 +944,17 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
   const Item* it = c.d_items + L.first;
   const dim3 g(L.count);
   if constexpr (sizeof(T) == 4) {
+    if (a.grad_slot < SLOT_NONE) {
+      // the adjoint's ring sweeps with the gradient partials (the plan asks
+      // for them only when every stencil launch is a ring sweep)
+      switch (L.variant) {
+        case 9: k_stencil_sweep4<T, R, 16, 8, 8, 512, true><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+        case 10: k_stencil_sweep4<T, R, 16, 8, 8, 256, true><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+        case 12: k_stencil_sweep4<T, R, 16, 8, 8, 1024, true><<<g, 1024, 0, c.s>>>(c.d_desc, it, a); break;
+        default: k_stencil_sweep4<T, R, 16, 16, 8, 512, true><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
+      }
+      return;
+    }
     switch (L.variant) {
       case 0: k_stencil_sweep<T, R, 16, 16, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
       case 1: k_stencil_sweep<T, R, 8, 16, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
@@ -937,6 +967,7 @@ void launch_stencil_r(const Ctx& c, const Launch& L, const StencilArgs& a) {
       case 8: k_stencil_sweep3<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 9: k_stencil_sweep4<T, R, 16, 8, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
       case 10: k_stencil_sweep4<T, R, 16, 8, 8, 256><<<g, 256, 0, c.s>>>(c.d_desc, it, a); break;
+      case 12: k_stencil_sweep4<T, R, 16, 8, 8, 1024><<<g, 1024, 0, c.s>>>(c.d_desc, it, a); break;
       default: k_stencil_sweep4<T, R, 16, 16, 8, 512><<<g, 512, 0, c.s>>>(c.d_desc, it, a); break;
     }
   } else {
@@ -1150,7 +1181,7 @@ constexpr int kScaleKnown = 1, kScaleGather = 2;
 template <typename T>
 void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double cre, double cim,
                  int occ_scale, int step, int want_energy, int want_density = 0, bool nonlocal = true,
-                 int fp16_scale = 0) {
+                 int fp16_scale = 0, int grad_slot = SLOT_NONE, double gre = 0.0, double gim = 0.0) {
   const int prec = c.P->prec;
   const bool nl = nonlocal && c.P->any_proj;
   if (nl) {
@@ -1164,7 +1195,8 @@ void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double c
     }
     launch_reduce<T>(c, cre, cim, occ_scale, want_energy);
   }
-  StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy, want_density};
+  StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy, want_density,
+                 grad_slot, gre, gim};
   launch_stencil<T>(c, sa);
   if (nl) {
     if (prec == DCMESH_SPLIT_BF16)
@@ -1726,14 +1758,21 @@ int dcmesh_adjoint_step(const dcmesh_domain* doms, int32_t n_dom, int32_t precis
     const int u_of[5] = {-1, SLOT_B2, SLOT_B1, SLOT_B0, SLOT_PSI};
     const int bufs[2] = {SLOT_B3, SLOT_B4};
     int mu_prev = SLOT_LAMBDA;
+    // With the ring sweep the partials come from the sweep that applies H to
+    // mu_{j-1}, as Re(c_j sum conj((-i D1 + A) mu_{j-1}) u_j) (the operator is
+    // Hermitian); otherwise a separate pass forms them before that sweep.
     for (int j = 1; j <= 4; ++j) {
-      launch_grad<T>(c, mu_prev, u_of[j], 0.0, -dt / j);
+      const int mu_new = bufs[(j - 1) % 2];
+      if (c.P->grad_fused) {
+        apply_stage<T>(c, mu_prev, SLOT_NONE, mu_new, 0.0, dt / j, 0, 0, 0, 0, true, 0, u_of[j], 0.0, -dt / j);
+      } else {
+        launch_grad<T>(c, mu_prev, u_of[j], 0.0, -dt / j);
+      }
       {
         ProfScope prof_(DCMESH_FAM_ADJOINT, c.s);
         k_grad_final<<<a_per_domain ? n_dom : 1, kBlock, 0, c.s>>>(c.d_desc, n_dom, a_per_domain ? 0 : 1);
       }
-      const int mu_new = bufs[(j - 1) % 2];
-      apply_stage<T>(c, mu_prev, SLOT_NONE, mu_new, 0.0, dt / j, 0, 0, 0);
+      if (!c.P->grad_fused) apply_stage<T>(c, mu_prev, SLOT_NONE, mu_new, 0.0, dt / j, 0, 0, 0);
       launch_axpy<T>(c, mu_new, SLOT_LAMBDA);
       mu_prev = mu_new;
     }

@@ -33,6 +33,13 @@ struct StencilArgs {
   int step;                         // A sample index
   int want_energy;                  // accumulate f_n Re(conj(u) H_loc u)
   int want_density;                 // write density / current partials of u
+  // pulse-gradient partials formed in the sweep (ring sweep only): with v the
+  // psi-sized buffer in grad_slot and g the gradient coefficient, block
+  // partials of Re(g sum conj((-i D1_d + A_d) u) v), d = x, y, z, go to
+  // D.g_part at the item's slot.  (-i D1_d + A_d) is Hermitian on the periodic
+  // grid, so the sum equals Re(g sum conj(u) (-i D1_d + A_d) v).
+  int grad_slot = SLOT_NONE;
+  double gre = 0, gim = 0;
 };
 
 template <typename T>
@@ -649,7 +656,7 @@ __device__ __forceinline__ void with_phases(F&& f, std::integer_sequence<int, Ps
   f(std::integral_constant<int, Ps>{}...);
 }
 
-template <typename T, int R, int OC, int TX, int TY, int NT, int GM, bool HB, bool EN>
+template <typename T, int R, int OC, int TX, int TY, int NT, int GM, bool HB, bool EN, bool GR>
 __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, const StencilArgs& args,
                                             const StencilW<T>& w, Cplx<T>* lds, double* red) {
   using C = Cplx<T>;
@@ -667,6 +674,9 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
   const bool base_is_u = args.base_slot == args.u_slot;
   const char* __restrict__ ub = (const char*)D.slot[args.u_slot];
   const char* __restrict__ bb = HB ? (const char*)D.slot[args.base_slot] : nullptr;
+  // GR: the gradient partner v, read at each owned point (needs all three axes)
+  static_assert(!GR || GM == 7, "the gradient partials need every axis");
+  const char* __restrict__ gb = GR ? (const char*)D.slot[args.grad_slot] : nullptr;
   char* __restrict__ ob = (char*)D.slot[args.out_slot];
   const char* __restrict__ vb = (const char*)D.v;
   const T* __restrict__ occ = (const T*)D.occ;
@@ -719,12 +729,14 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
   C hq[KH][H];         // halo of plane p in slot (p - z_begin) % H
   C bq[KP][2];         // base of plane p in slot (p - z_begin) % 2
   T vq[KP][2];         // potential of plane p in slot (p - z_begin) % 2
+  C gq[KP][2];         // GR: gradient partner of plane p in slot (p - z_begin) % 2
 
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
 #pragma unroll
     for (int s = 0; s < 2 * R + 1; ++s) q[k][s] = at(ub, wrap(z_begin - R + s, nz), co[k]);
     if constexpr (HB) bq[k][0] = at(bb, z_begin, co[k]);
+    if constexpr (GR) gq[k][0] = at(gb, z_begin, co[k]);
     vq[k][0] = vat(z_begin, cv[k]);
     lds[lc[k]] = q[k][R];
   }
@@ -737,6 +749,7 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
   lds_barrier();
 
   double e_acc = 0.0;
+  double g_acc[3] = {0.0, 0.0, 0.0};
   // one plane at phase P = (z - z_begin) % U; false once the segment is done
   auto plane_step = [&](auto PC, int z) -> bool {
     constexpr int P = decltype(PC)::value;
@@ -749,6 +762,7 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
       for (int k = 0; k < KP; ++k) {
         q[k][(P + 2 * R + 1) % U] = at(ub, zq, co[k]);
         if constexpr (HB) bq[k][(P + 1) % 2] = at(bb, zn, co[k]);
+        if constexpr (GR) gq[k][(P + 1) % 2] = at(gb, zn, co[k]);
         vq[k][(P + 1) % 2] = vat(zn, cv[k]);
       }
 #pragma unroll
@@ -793,6 +807,17 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
         }
       }
       if (ok[k]) {
+        if constexpr (GR) {
+          // t_d = (-i D1_d + A_d) u at this point; conj(t_d) v, times the coefficient
+          const C v = gq[k][P % 2];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const T tre = w.A[d] * c0.re + G[d].im, tim = w.A[d] * c0.im - G[d].re;
+            const double pr = (double)tre * v.re + (double)tim * v.im;
+            const double pi = (double)tre * v.im - (double)tim * v.re;
+            g_acc[d] += args.gre * pr - args.gim * pi;
+          }
+        }
         if constexpr (EN) e_acc += (double)fn * ((double)c0.re * acc.re + (double)c0.im * acc.im);
         if (args.occ_scale) { acc.re *= fn; acc.im *= fn; }
         C b = base_is_u ? c0 : C{0, 0};
@@ -821,9 +846,19 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
     const double s = block_sum<double, NT / kWave>(e_acc, red);
     if (threadIdx.x == 0) D.e_loc[e_loc_slot<TX, TY>(D, it)] = s;
   }
+  if constexpr (GR) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double s = block_sum<double, NT / kWave>(g_acc[d], red);
+      if (threadIdx.x == 0) D.g_part[(long long)e_loc_slot<TX, TY>(D, it) * 3 + d] = s;
+    }
+  }
 }
 
-template <typename T, int R, int OC, int TX, int TY, int NT>
+// GRK: the adjoint's sweep (every axis, no energy or density, the pulse-gradient
+// partials of args.grad_slot formed in passing); a kernel of its own, so the
+// extra registers it needs do not weigh on the other sweeps.
+template <typename T, int R, int OC, int TX, int TY, int NT, bool GRK = false>
 __global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict__ doms,
                                                        const Item* __restrict__ items,
                                                        StencilArgs args) {
@@ -843,11 +878,11 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict
   auto body = [&](auto hbc, auto enc) __attribute__((always_inline)) {
     constexpr bool HB = decltype(hbc)::value, EN = decltype(enc)::value;
     if (args.want_density || w.A[0] != (T)0 || w.A[1] != (T)0)
-      sweep4_body<T, R, OC, TX, TY, NT, 7, HB, EN>(D, it, args, w, lds, red);
+      sweep4_body<T, R, OC, TX, TY, NT, 7, HB, EN, false>(D, it, args, w, lds, red);
     else if (w.A[2] != (T)0)
-      sweep4_body<T, R, OC, TX, TY, NT, 4, HB, EN>(D, it, args, w, lds, red);
+      sweep4_body<T, R, OC, TX, TY, NT, 4, HB, EN, false>(D, it, args, w, lds, red);
     else
-      sweep4_body<T, R, OC, TX, TY, NT, 0, HB, EN>(D, it, args, w, lds, red);
+      sweep4_body<T, R, OC, TX, TY, NT, 0, HB, EN, false>(D, it, args, w, lds, red);
   };
   auto with_en = [&](auto hbc) __attribute__((always_inline)) {
     if (args.want_energy)
@@ -855,10 +890,16 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict
     else
       body(hbc, std::false_type{});
   };
-  if (hb)
+  if constexpr (GRK) {
+    if (hb)
+      sweep4_body<T, R, OC, TX, TY, NT, 7, true, false, true>(D, it, args, w, lds, red);
+    else
+      sweep4_body<T, R, OC, TX, TY, NT, 7, false, false, true>(D, it, args, w, lds, red);
+  } else if (hb) {
     with_en(std::true_type{});
-  else
+  } else {
     with_en(std::false_type{});
+  }
 }
 
 // rho[g] = sum_chunks dpart[c][g][0];  j[g][d] = sum_chunks dpart[c][g][1 + d] + A_d rho.
