@@ -1195,6 +1195,9 @@ void apply_stage(const Ctx& c, int u_slot, int base_slot, int out_slot, double c
     }
     launch_reduce<T>(c, cre, cim, occ_scale, want_energy);
   }
+  // grad_slot: only the adjoint's FP32 / split sweeps of mu ask for gradient
+  // partials, with no base term, energy or density (the gradient sweep kernel
+  // has none of them)
   StencilArgs sa{u_slot, base_slot, out_slot, cre, cim, occ_scale, step, want_energy, want_density,
                  grad_slot, gre, gim};
   launch_stencil<T>(c, sa);

@@ -855,9 +855,9 @@ __device__ __forceinline__ void sweep4_body(const DomDesc& D, const Item& it, co
   }
 }
 
-// GRK: the adjoint's sweep (every axis, no energy or density, the pulse-gradient
-// partials of args.grad_slot formed in passing); a kernel of its own, so the
-// extra registers it needs do not weigh on the other sweeps.
+// GRK: the adjoint's sweep (every axis, no base, energy or density, the
+// pulse-gradient partials of args.grad_slot formed in passing); a kernel of its
+// own, so the extra registers it needs do not weigh on the other sweeps.
 template <typename T, int R, int OC, int TX, int TY, int NT, bool GRK = false>
 __global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict__ doms,
                                                        const Item* __restrict__ items,
@@ -891,10 +891,8 @@ __global__ __launch_bounds__(NT) void k_stencil_sweep4(const DomDesc* __restrict
       body(hbc, std::false_type{});
   };
   if constexpr (GRK) {
-    if (hb)
-      sweep4_body<T, R, OC, TX, TY, NT, 7, true, false, true>(D, it, args, w, lds, red);
-    else
-      sweep4_body<T, R, OC, TX, TY, NT, 7, false, false, true>(D, it, args, w, lds, red);
+    // the adjoint applies H to mu with no base term (the host passes none)
+    sweep4_body<T, R, OC, TX, TY, NT, 7, false, false, true>(D, it, args, w, lds, red);
   } else if (hb) {
     with_en(std::true_type{});
   } else {
