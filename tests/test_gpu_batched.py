@@ -140,3 +140,51 @@ def test_stencil_work_orders_give_identical_results(doms, zseg):
     _, ob = P.propagate(od, a_mid, 0.02, od.psi, want_energy=True)
     e = o0[0]["energy"].cpu().numpy()
     assert np.abs(e - ob["energy"]).max() < 1e-5 * np.abs(ob["energy"]).max()
+
+
+@pytest.mark.parametrize("a_per_domain", [False, True])
+def test_batched_adjoint_gradient_matches_single_domains_and_oracle(doms, a_per_domain):
+    """One adjoint step over 12 of the subset's domains at once (enough
+    (domain, z segment) clusters for the per-XCD stencil order, gradient
+    partials formed in the sweeps): lambda of every domain equals its
+    single-domain call bitwise, the gradient (per domain, or summed over the
+    batch) agrees with the single-domain gradients to FP64 rounding (a domain
+    alone gets z segments to fill the GPU, so its block partials group the
+    same terms differently), and the first domain's gradient agrees with the
+    oracle's."""
+    import torch
+    import paper_2509_00966_amd as api
+    from oracle import adjoint as ADJ
+    sub = doms[:12]
+    dt = 0.02
+    A = np.array([0.03, -0.02, 0.06])
+    rng = np.random.default_rng(406)
+    lams = [(rng.standard_normal(d.psi.shape) + 1j * rng.standard_normal(d.psi.shape)) * 0.05 for d in sub]
+    gs = [to_device(d, "fp32") for d in sub]
+    lam_b = [torch.from_numpy(l).to("cuda", torch.complex64) for l in lams]
+    n = len(sub)
+    a = a_tensor(np.tile(A, (n, 1, 1)) if a_per_domain else A[None])
+    grad_b = torch.zeros((n, 3) if a_per_domain else (3,), dtype=torch.float64, device="cuda")
+    ws = api.Workspace.for_domains(gs, "fp32")
+    api.adjoint_step(gs, lam_b, a.contiguous(), dt, grad_b, "fp32", ws, a_per_domain=a_per_domain)
+    torch.cuda.synchronize()
+    singles = []
+    for d, g, l in zip(sub, gs, lams):
+        lam_s = torch.from_numpy(l).to("cuda", torch.complex64)
+        grad_s = torch.zeros(3, dtype=torch.float64, device="cuda")
+        w1 = api.Workspace.for_domains([g], "fp32")
+        api.adjoint_step([g], [lam_s], a_tensor(A[None]), dt, grad_s, "fp32", w1)
+        torch.cuda.synchronize()
+        singles.append((lam_s, grad_s.cpu().numpy()))
+    for i, (lb, (ls, gsn)) in enumerate(zip(lam_b, singles)):
+        assert torch.equal(lb, ls), i
+        if a_per_domain:
+            assert np.abs(grad_b[i].cpu().numpy() - gsn).max() <= 1e-12 * np.abs(gsn).max(), i
+    if not a_per_domain:
+        total = np.sum([g for _, g in singles], axis=0)
+        assert np.abs(grad_b.cpu().numpy() - total).max() <= 1e-12 * np.abs(total).max()
+    od = oracle_inputs(sub[0], "fp32")
+    lam_in = lams[0].astype(np.complex64).astype(np.complex128)
+    _, g_ref = ADJ.adjoint_step(od, A, dt, od.psi, lam_in)
+    g0 = singles[0][1]
+    assert np.abs(g0 - g_ref).max() < 1e-4 * np.abs(g_ref).max()
