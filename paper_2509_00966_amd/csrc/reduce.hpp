@@ -240,7 +240,8 @@ __global__ void k_fill_int(int* p, int v) { *p = v; }
 namespace dcm {
 
 // Column norms of the psi slot: partial sums of |psi[g][n]|^2 over 256 grid
-// rows per block, one FP64 value per (block, orbital).  Items: (dom, row block).
+// rows per block, one FP64 value per (block, orbital), in a fixed order.
+// Items: (dom, row block).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_colnorm_partial(const DomDesc* __restrict__ doms,
                                                             const Item* __restrict__ items) {
@@ -250,13 +251,42 @@ __global__ __launch_bounds__(kBlock) void k_colnorm_partial(const DomDesc* __res
   const int no = D.n_orb;
   const long long g0 = (long long)it.a * kBlock, g1 = min(g0 + kBlock, D.n_grid);
   const C* __restrict__ psi = (const C*)D.slot[SLOT_PSI];
-  for (int n = threadIdx.x; n < no; n += kBlock) {
-    double s = 0;
-    for (long long g = g0; g < g1; ++g) {
-      const C c = psi[g * no + n];
+  const int rows = (int)(g1 - g0);
+  double* __restrict__ part = D.cn_part + (long long)(blockIdx.x - D.item0_rows) * no;
+  if (no > kBlock / 2) {
+    for (int n = threadIdx.x; n < no; n += kBlock) {
+      // rows in order; unrolled so that eight loads are in flight per thread
+      double s = 0;
+      const C* __restrict__ col = psi + g0 * no + n;
+#pragma unroll 8
+      for (int r = 0; r < rows; ++r) {
+        const C c = col[(long long)r * no];
+        s += (double)c.re * c.re + (double)c.im * c.im;
+      }
+      part[n] = s;
+    }
+    return;
+  }
+  // no <= 128: ph = kBlock / no threads per orbital, thread (p, n) summing rows
+  // p, p + ph, ... (so a wave's loads cover whole consecutive rows); the ph
+  // sums of an orbital are then added in p order
+  __shared__ double red[kBlock];
+  const int ph = kBlock / no, p = threadIdx.x / no, n = threadIdx.x % no;
+  double s = 0;
+  if (p < ph) {
+    const C* __restrict__ col = psi + g0 * no + n;
+#pragma unroll 8
+    for (int r = p; r < rows; r += ph) {
+      const C c = col[(long long)r * no];
       s += (double)c.re * c.re + (double)c.im * c.im;
     }
-    D.cn_part[(long long)(blockIdx.x - D.item0_rows) * no + n] = s;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < no) {
+    double t = 0;
+    for (int q = 0; q < ph; ++q) t += red[q * no + threadIdx.x];
+    part[threadIdx.x] = t;
   }
 }
 
@@ -266,9 +296,13 @@ __global__ __launch_bounds__(kBlock) void k_colnorm_final(const DomDesc* __restr
   const DomDesc& D = doms[items[blockIdx.x].dom];
   const int no = D.n_orb;
   const double h3 = D.h * D.h * D.h;
+  const int nb = D.n_rows_blocks;
   for (int n = threadIdx.x; n < no; n += kBlock) {
+    // block order; unrolled so that sixteen loads are in flight per thread
     double s = 0;
-    for (int b = 0; b < D.n_rows_blocks; ++b) s += D.cn_part[(long long)b * no + n];
+    const double* __restrict__ col = D.cn_part + n;
+#pragma unroll 16
+    for (int b = 0; b < nb; ++b) s += col[(long long)b * no];
     D.cn_inv[n] = 1.0 / sqrt(h3 * s);
   }
 }
@@ -282,11 +316,18 @@ __global__ __launch_bounds__(kBlock) void k_colnorm_scale(const DomDesc* __restr
   const DomDesc& D = doms[it.dom];
   const int no = D.n_orb;
   const long long g0 = (long long)it.a * kBlock, g1 = min(g0 + kBlock, D.n_grid);
-  C* __restrict__ psi = (C*)D.slot[SLOT_PSI];
-  for (long long e = g0 * no + threadIdx.x; e < g1 * no; e += kBlock) {
-    const T s = (T)D.cn_inv[e % no];
+  C* __restrict__ psi = (C*)D.slot[SLOT_PSI] + g0 * no;
+  // element e of the block's rows is orbital e mod no; stepping e by the block
+  // size steps the orbital by kBlock mod no (one conditional wrap), so no
+  // 64-bit division per element
+  const int count = (int)((g1 - g0) * no), step = kBlock % no;
+  int n = threadIdx.x % no;
+  for (int e = threadIdx.x; e < count; e += kBlock) {
+    const T s = (T)D.cn_inv[n];
     psi[e].re *= s;
     psi[e].im *= s;
+    n += step;
+    if (n >= no) n -= no;
   }
 }
 
