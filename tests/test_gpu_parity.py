@@ -156,15 +156,17 @@ def test_adjoint_step_matches_oracle(api, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
-@pytest.mark.parametrize("stencil", [-1, 11, 2])
-def test_adjoint_gradient_from_sweep_and_from_separate_pass(api, precision, stencil):
+@pytest.mark.parametrize("stencil", [-1, 9, 10, 11, 12, 2])
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_adjoint_gradient_from_sweep_and_from_separate_pass(api, precision, stencil, order):
     """The pulse gradient with its partials formed inside the ring sweeps
-    (default and variant 11; the sweep applies (-i D1 + A) to mu and pairs it
-    with u, the operator being Hermitian) and by the separate pass (variant 2,
-    not a ring sweep): both against the oracle, on a ragged domain with a field
-    along every axis (so every gradient axis matters), then each other."""
+    (default and every ring-sweep tile, 9-12; the sweep applies (-i D1 + A) to
+    mu and pairs it with u, the operator being Hermitian) and by the separate
+    pass (variant 2, not a ring sweep), at each FD order: against the oracle,
+    on a ragged domain with a field along every axis (so every gradient axis
+    matters)."""
     torch = _torch()
-    dom = make_domain(37, (19, 13, 21), 21, 3, proj_per_atom=8, h=0.4, fd_order=6)
+    dom = make_domain(37, (19, 13, 21), 21, 3, proj_per_atom=8, h=0.4, fd_order=order)
     A = np.array([0.05, -0.04, 0.07])
     dt = 0.02
     rng = np.random.default_rng(38)
@@ -187,7 +189,7 @@ def test_adjoint_gradient_from_sweep_and_from_separate_pass(api, precision, sten
     tol = {"fp32": TOL_OP["fp32"], "split_bf16": 2e-5}[precision]
     assert_close(_np(lam_d), lam_ref, tol * 5, label=f"lambda stencil={stencil}")
     err = np.abs(_np(grad) - g_ref).max() / np.abs(g_ref).max()
-    print(f"[parity] gradient stencil={stencil} {precision}: {err:.2e}")
+    print(f"[parity] gradient stencil={stencil} FD{order} {precision}: {err:.2e}")
     assert err < tol * 50
 
 
