@@ -197,6 +197,7 @@ def main():
         "psi_finite": finite,
         "cpu_baseline": cpu,
     }
+    out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out))
 
 
@@ -286,6 +287,7 @@ def run_hpsi(args):
         "stream_copy_GBs": st["copy"]["TB/s"] * 1e3,
         "frac_of_copy_stream": achieved / (st["copy"]["TB/s"] * 1e3),
     }
+    out_line["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out_line))
 
 
@@ -335,6 +337,7 @@ def run_eq2(args):
                          "correction_CGEMM2": kernels.get("correct", {}).get("algorithmic_tflops")},
         "psi_finite": bool(torch.isfinite(g.psi).all().item()),
     }
+    out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out))
 
 
@@ -518,6 +521,7 @@ def run_adjoint(args):
         "forward_ms": sum(fw) / reps, "backward_ms": sum(bw) / reps,
         "loss": loss, "grad_norm": float(grad.norm().item()), "grad_finite": bool(torch.isfinite(grad).all().item()),
     }
+    out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out))
 
 
@@ -675,6 +679,7 @@ def run_batched(args):
                      "speedup_vs_" + precs[0]: r["value"] / main["value"], "roofline": r["roofline"],
                      "kernels": r["kernels"], "kernel_ms_per_step": r["kernel_ms_per_step"],
                      "psi_finite": r["psi_finite"]}
+    out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out))
 
 
