@@ -10,7 +10,7 @@ the three error views of each precision (relative Frobenius norm,
 element-wise max over the largest value, worst orbital) are written as one
 JSON line.
 
-    python tests/error_curve.py [--steps 200] [--out gpurun_out/error_curve.jsonl]
+    python tests/error_curve.py [--steps 200] [--out error_curve.jsonl]
 
 Not collected by pytest (it takes minutes of oracle time); it needs a GPU.
 """
@@ -31,7 +31,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--sample", type=int, default=8)
-    ap.add_argument("--out", default=os.path.join("gpurun_out", "error_curve.jsonl"))
+    ap.add_argument("--out", default="error_curve.jsonl")
     args = ap.parse_args()
 
     import torch
